@@ -1,0 +1,198 @@
+"""Benchmark of the per-time-step hot path on one MI355X.
+
+A "step" is one full time step of eq. (4): ionic update and ion term, right-hand
+side, and the two-level additive Schwarz PCG to relative residual 1e-10 from
+x0 = U^k -- all in libpdg's HIP kernels.  Workload (default): 3-D cube [0, 10 mm]^3,
+40^3 cubes agglomerated into ~8,000 polyhedra, p = 2 (~80k dofs), two tissue
+regions (conductivity 1:3), 64 subdomains of uneven size (+-40 %) with a P1
+coarse space on them, planar stimulus, plain FP64.
+
+Prints one JSON line (see the design doc for the fields).  Inputs are resident in
+HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time per CN step & MDoF/s at relres 1e-10; PCG iters; % HBM roofline vs FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_2512_19536_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload_tag, n_launch_bytes):
+    """HBM bytes per Schwarz-apply launch from the committed counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"schwarz_apply_{workload_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(problem, n_steps=1):
+    """The FP64 oracle (as it stands) on the host cores: setup untimed, then
+    `n_steps` time steps timed."""
+    from oracle.monodomain import Monodomain
+    cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = cores
+    t0 = time.perf_counter()
+    md = Monodomain(problem)
+    t_setup = time.perf_counter() - t0
+    U, Up, Y = md.initial_state()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(n_steps):
+        U, Up, Y, info = md.step(U, Up, Y)
+        iters.append(info.iters)
+    dt = (time.perf_counter() - t0) / n_steps
+    return {
+        "value": problem.n_dof / dt / 1e6,
+        "unit": "MDoF/s",
+        "cores": int(min(cores, blas_threads)),
+        "kind": "oracle",
+        "sample": f"first {n_steps} CN step(s) of the same workload (oracle setup {t_setup:.1f} s untimed); "
+                  f"s/step {dt:.2f}, PCG iters {iters}; scipy.sparse SpMV single-threaded, dense "
+                  f"Cholesky solves on {blas_threads} BLAS threads of {cores} host cores",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--local-prec", default=None, choices=["f64", "f32", "bf16"])
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; a multi-GPU run is not provided "
+              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2512_19536_amd import _lib, from_problem, initial_state
+    from pdg_inputs import problems
+
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    pr = problems.BUILDERS[args.workload]()
+    if args.local_prec:
+        pr.local_prec = args.local_prec
+        pr.coarse_prec = "f64" if args.local_prec == "f64" else "f32"
+    log(f"[bench] workload {pr.name}: {pr.n_elem} elements, p={pr.p}, {pr.n_dof} dofs, "
+        f"{pr.n_sub} subdomains; inputs {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    ctx = from_problem(pr, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] library setup (assembly, Schwarz inverses, upload) {time.perf_counter() - t0:.1f} s")
+    U, Up, Y = initial_state(ctx, pr)
+    stream = ctx.stream
+    for k in range(args.warmup):
+        info = ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
+        log(f"[bench] warmup step {k}: iters {info['iters']}")
+    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 1)
+    ctx.kernel_timing()  # reset
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    iters = []
+    ev0.record(stream)
+    for k in range(args.steps):
+        info = ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
+        iters.append(info["iters"])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    n_launch, k_ms, k_bytes = ctx.kernel_timing()
+    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 0)
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, iters {iters}")
+    k_avg_ms = k_ms / max(n_launch, 1)
+    achieved = k_bytes / (k_avg_ms * 1e-3) / 1e9 if n_launch else 0.0
+    log(f"[bench] schwarz apply: {n_launch} launches, avg {k_avg_ms * 1e3:.1f} us, {k_bytes / 1e6:.1f} MB "
+        f"-> {achieved:.0f} GB/s")
+
+    # plain copy of known size, for calibrating HBM byte counters in profiles
+    nb = args.copy_calibration_mb * (1 << 20)
+    src = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+    tag = pr.name + ("" if pr.local_prec == "f64" else "_" + pr.local_prec)
+    traffic = traffic_from_profiles(tag, k_bytes)
+    roof = {
+        "kernel": "k_schwarz (local + coarse inverse-tile products)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": int(k_bytes),
+        "avg_launch_us": round(k_avg_ms * 1e3, 2),
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle ...")
+        cpu = cpu_baseline(pr, args.cpu_steps)
+        log(f"[bench] cpu baseline: {cpu['value']:.4f} MDoF/s")
+    dtype = {"f64": "f64", "f32": "f64+f32-schwarz", "bf16": "f64+bf16-schwarz"}[pr.local_prec]
+    out = {
+        "metric": METRIC,
+        "value": round(pr.n_dof / (ms_step * 1e-3) / 1e6, 3),
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{pr.name}: {'3-D' if pr.mesh.dim == 3 else '2-D'} polytopal mesh, {pr.n_elem} elements, "
+                         f"p={pr.p}, {pr.n_dof} dofs, {pr.n_sub} subdomains + P1 coarse, "
+                         f"Schwarz {pr.local_prec}/{pr.coarse_prec}, relres {pr.tol:g}"),
+            "n_dof": pr.n_dof, "n_elem": pr.n_elem, "p": pr.p, "n_sub": pr.n_sub,
+        },
+        "pcg_iters": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

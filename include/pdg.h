@@ -1,0 +1,232 @@
+/*
+ * pdg.h -- C-ABI of the MI355X (gfx950) library for the per-time-step solve of
+ * the Crank-Nicolson / SIPG-PolyDG monodomain system with the two-level
+ * non-overlapping additive Schwarz preconditioned conjugate gradient.
+ *
+ * Paper: "A massively parallel non-overlapping Schwarz preconditioner for
+ * PolyDG methods in brain electrophysiology" (arXiv 2512.19536).
+ *   - model: Section 2, eq. (1);
+ *   - discretisation: Section 3, eqs. (2)-(4);
+ *   - preconditioner: Section 4, eq. (5);
+ *   - solver and stopping rule: Sections 4-5.
+ *
+ * Conventions shared by every call
+ *   - Every call returns a pdg_status; no C++ exception crosses the ABI.  On
+ *     error pdg_last_error(ctx) returns a message.
+ *   - Call order: pdg_create -> pdg_set_mesh -> pdg_assemble -> [pdg_set_ionic]
+ *     -> pdg_setup_preconditioner -> pdg_workspace_query -> pdg_bind_workspace
+ *     -> compute calls.  Out-of-order calls return PDG_ESTATE.
+ *   - Host arrays passed in are copied; the caller keeps ownership.
+ *   - "Device" pointers are HIP device memory owned by the caller (e.g. torch
+ *     tensors).  The library reads/writes them only on the stream given to
+ *     pdg_create.  The library never allocates device memory itself: all of its
+ *     device state lives in the single workspace bound by pdg_bind_workspace.
+ *   - Coefficient vectors are element-major: entry (e, i) at e*nd + i, where i
+ *     indexes the modal basis of element e (Legendre polynomials of total
+ *     degree <= p on the element's bounding box, orthonormal on the box;
+ *     ordering: total degree ascending, then alpha_1 descending, then
+ *     alpha_2 descending).  Ionic states are [5][n_elem][nd] (state-major).
+ *   - A context is not thread-safe.  Separate contexts may use separate streams.
+ *   - Compute calls are asynchronous with respect to the host except where
+ *     stated (pdg_solve and pdg_step synchronise the stream to report
+ *     iteration counts).
+ */
+#ifndef PDG_H
+#define PDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdg_ctx pdg_ctx;
+
+typedef enum {
+    PDG_OK = 0,
+    PDG_EINVAL = -1,      /* bad argument (size, pointer, value, label)           */
+    PDG_ENOMEM = -2,      /* workspace too small / host allocation failed          */
+    PDG_EHIP = -3,        /* a HIP runtime call failed                             */
+    PDG_ENOTSPD = -4,     /* a Cholesky pivot <= 0 during setup                    */
+    PDG_ENOCONV = -5,     /* PCG hit maxit; x holds the last iterate               */
+    PDG_EBREAKDOWN = -6,  /* (p, K p) <= 0 or (r, z) <= 0 inside PCG               */
+    PDG_ENONFINITE = -7,  /* NaN/Inf in PCG scalars, or a non-positive ionic
+                             concentration before a logarithm                      */
+    PDG_ESTATE = -8       /* call out of order / no GPU bound                      */
+} pdg_status;
+
+typedef enum { PDG_F64 = 0, PDG_F32 = 1, PDG_BF16 = 2 } pdg_precision;
+
+typedef struct {
+    int32_t iters;        /* PCG iterations performed (0 if x0 already met tol)    */
+    double relres;        /* ||r_k|| / ||b|| of the recurrence residual            */
+    double true_relres;   /* ||b - K x|| / ||b|| if requested, else -1             */
+    double bnorm;         /* ||b||                                                 */
+} pdg_solve_info;
+
+/* Create a context on HIP device `hip_device`, launching on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  hip_device = -1 creates a
+ * host-only context: setup calls work, compute calls return PDG_ESTATE. */
+pdg_status pdg_create(pdg_ctx **out, int32_t hip_device, void *hip_stream);
+void pdg_destroy(pdg_ctx *ctx);
+const char *pdg_last_error(const pdg_ctx *ctx);
+const char *pdg_status_string(int32_t status);
+
+/* ------------------------------------------------------------------------
+ * 1. Mesh and degree (Section 3: polytopal mesh T_h, broken space P^p).
+ * Each element is a union of sub-cells: triangles (dim 2) or axis-aligned
+ * boxes (dim 3).  Facets are the pieces of element boundaries: segments
+ * (dim 2) or axis-aligned rectangles (dim 3); only interior facets
+ * (plus >= 0) enter the SIPG form (homogeneous Neumann condition, eq. (1)).
+ *   cell_ptr     [n_elem+1]            CSR over sub-cells
+ *   cell_geom    dim 2: [n_cell][3][2] triangle vertices
+ *                dim 3: [n_cell][2][3] box lo corner, hi corner
+ *   facet_elem   [n_facet][2]          minus, plus (plus = -1 on the boundary)
+ *   facet_geom   dim 2: [n_facet][2][2] end points; dim 3: [n_facet][2][3] lo, hi
+ *   facet_normal [n_facet][dim]        unit normal from minus to plus
+ *   sigma        [n_elem][dim][dim]    SPD conductivity tensor, constant per element
+ * Errors: PDG_EINVAL for dim not in {2,3}, p not in 1..4, empty element,
+ * out-of-range element index, non-unit normal, non-SPD sigma. */
+typedef struct {
+    int32_t dim;
+    int64_t n_elem;
+    const int64_t *cell_ptr;
+    const double *cell_geom;
+    int64_t n_facet;
+    const int64_t *facet_elem;
+    const double *facet_geom;
+    const double *facet_normal;
+    const double *sigma;
+} pdg_mesh;
+
+pdg_status pdg_set_mesh(pdg_ctx *ctx, const pdg_mesh *mesh, int32_t p);
+
+/* Sizes after pdg_set_mesh (any pointer may be NULL). */
+pdg_status pdg_get_sizes(const pdg_ctx *ctx, int64_t *n_elem, int32_t *nd, int64_t *n_dof,
+                         int64_t *nnz_blocks);
+
+/* ------------------------------------------------------------------------
+ * 2. Assembly (Section 3): K = (chi_m C_m / dt) M + 1/2 A, i.e. the paper's
+ * K_h = C_m chi_m M_h + dt/2 A_h divided by dt.  A is the SIPG form of
+ * eq. (3) with the penalty of eq. (2): eta = eta0 {Sigma_K}_A p^2 / {h_K}_H,
+ * Sigma_K = largest eigenvalue of sigma on K, h_K = element diameter.
+ * Quadrature: 2-D sub-triangles by the collapsed (Duffy) map with (p+2)^2
+ * Gauss points, 3-D sub-boxes with (p+1)^3 points; facets with p+2 (2-D) or
+ * (p+1)^2 (3-D) points.  Host computation; stored as block-sparse rows of
+ * nd x nd element blocks (diagonal block first). */
+pdg_status pdg_assemble(pdg_ctx *ctx, double chi_m, double c_m, double dt, double eta0);
+
+/* Host copies of the assembled operators (for checking): row_ptr [n_elem+1],
+ * col [nnzb], val [nnzb][nd][nd] (row = test function, col = trial), mass
+ * blocks [n_elem][nd][nd].  Any pointer may be NULL. */
+pdg_status pdg_get_matrix(const pdg_ctx *ctx, int64_t *row_ptr, int32_t *col, double *val,
+                          double *mass);
+
+/* ------------------------------------------------------------------------
+ * Ionic model parameters (Section 2, Barreto-Cressman; the paper defers its
+ * equations to the cited works).  `params` holds n_params = 24 doubles in this
+ * order: g_Na, g_NaL, g_K, g_KL, g_AHP, g_ClL, g_Ca, V_Ca, phi, tau, beta,
+ * rho, G_glia, eps, k_bath, Cl_i, Cl_o, nernst, gamma, ca_tau, ca_coef,
+ * K_i0, Na_i0, Na_o0.  Required before pdg_step / pdg_ionic. */
+pdg_status pdg_set_ionic(pdg_ctx *ctx, const double *params, int32_t n_params);
+
+/* ------------------------------------------------------------------------
+ * 3. Two-level additive Schwarz preconditioner (Section 4, eq. (5)):
+ * B^{-1} = sum_i R_i^T K_i^{-1} R_i + P K_0^{-1} P^T with K_i the principal
+ * submatrix of K on the dofs of subdomain i, P the exact L^2 injection of
+ * P^q on each coarse agglomerate (same modal basis on the agglomerate's
+ * bounding box) and K_0 = P^T K P.  Local and coarse matrices are inverted
+ * densely on the host in FP64 (Cholesky); the inverses are stored as packed
+ * lower-triangular 64 x 64 tiles in `local_prec` / `coarse_prec`.
+ *   elem_sub    [n_elem] in 0..n_sub-1 (every subdomain non-empty)
+ *   elem_coarse [n_elem] in 0..n_coarse-1, or NULL = the subdomains
+ *   coarse_q    0 = one-level (no coarse correction), 1..p otherwise
+ * Errors: PDG_EINVAL (labels, sizes, subdomain larger than 6144 dofs),
+ * PDG_ENOTSPD (a Cholesky pivot <= 0). */
+typedef struct {
+    int32_t n_sub;
+    const int32_t *elem_sub;
+    int32_t n_coarse;
+    const int32_t *elem_coarse;
+    int32_t coarse_q;
+    int32_t local_prec;   /* pdg_precision */
+    int32_t coarse_prec;  /* pdg_precision (PDG_F64 or PDG_F32) */
+} pdg_precond_desc;
+
+pdg_status pdg_setup_preconditioner(pdg_ctx *ctx, const pdg_precond_desc *desc);
+
+/* Host copy of the FP64 inverse of subdomain `sub`'s matrix as a dense
+ * [n_i][n_i] array (dofs in element-label order), and of the coarse operator:
+ * P [n_elem][nd][nq0] and K_0 [N0][N0].  Sizes via pdg_get_precond_sizes. */
+pdg_status pdg_get_precond_sizes(const pdg_ctx *ctx, int32_t sub, int64_t *n_i, int64_t *n0,
+                                 int32_t *nq0);
+pdg_status pdg_get_local_inverse(const pdg_ctx *ctx, int32_t sub, double *out);
+pdg_status pdg_get_coarse(const pdg_ctx *ctx, double *P, double *K0);
+
+/* ------------------------------------------------------------------------
+ * Device memory: the library needs one workspace of `bytes` bytes (256-byte
+ * aligned) holding the matrix, the preconditioner, quadrature data and PCG
+ * vectors.  pdg_bind_workspace uploads the setup data into it on the stream.
+ * The caller must keep it alive and untouched until pdg_destroy. */
+pdg_status pdg_workspace_query(pdg_ctx *ctx, size_t *bytes);
+pdg_status pdg_bind_workspace(pdg_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Options (after pdg_create). */
+typedef enum {
+    PDG_OPT_TRUE_RESIDUAL = 1,  /* 1: pdg_solve/pdg_step compute ||b - Kx||/||b|| (one extra SpMV) */
+    PDG_OPT_CHUNK = 2,          /* PCG iterations launched between host convergence polls (>= 1) */
+    PDG_OPT_KERNEL_TIMING = 3   /* 1: time every Schwarz-apply launch with HIP events */
+} pdg_option;
+pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
+
+/* Kernel timing of the Schwarz-apply kernel (local + coarse tile products)
+ * accumulated while PDG_OPT_KERNEL_TIMING is on; reading resets it.
+ * Synchronises the stream. */
+pdg_status pdg_kernel_timing(pdg_ctx *ctx, int64_t *launches, double *total_ms,
+                             double *bytes_per_launch);
+
+/* ------------------------------------------------------------------------
+ * 4. Compute calls (device pointers, [n_elem][nd] coefficient vectors).
+ */
+
+/* coeff[c][e][:] = L^2 projection of the per-element constant vals[c][e]
+ * (vals: [ncomp][n_elem], coeff: [ncomp][n_elem][nd]).  Used for initial data. */
+pdg_status pdg_project_p0(pdg_ctx *ctx, const double *vals, int32_t ncomp, double *coeff);
+
+/* y = K x (block-sparse element SpMV). */
+pdg_status pdg_spmv(pdg_ctx *ctx, const double *x, double *y);
+
+/* z = B^{-1} r (eq. (5)): all local solves plus the coarse correction. */
+pdg_status pdg_precond_apply(pdg_ctx *ctx, const double *r, double *z);
+
+/* Ionic update (second line of eq. (4)) and ion term: ions [5][n_elem][nd]
+ * Y^k -> Y^(k+1) in place; I[e][i] = int_K f(u~, y^(k+1)) phi_i with the
+ * extrapolated potential u~ = (3 u^k - u^(k-1)) / 2.
+ * Returns PDG_ENONFINITE (synchronising) if a concentration was <= 0. */
+pdg_status pdg_ionic(pdg_ctx *ctx, const double *u, const double *u_prev, double *ions,
+                     double *I);
+
+/* b = 2 c M u - K u - chi_m I + f_ext (first line of eq. (4) divided by dt);
+ * f_ext may be NULL (= 0). */
+pdg_status pdg_rhs(pdg_ctx *ctx, const double *u, const double *I, const double *f_ext,
+                   double *b);
+
+/* Solve K x = rhs by PCG with B^{-1} (eq. (5)); x: in = initial guess, out =
+ * solution.  Stops when ||r_k|| <= tol ||rhs||.  ||rhs|| = 0 gives x = 0.
+ * Synchronises the stream.  PDG_ENOCONV: x holds the last iterate. */
+pdg_status pdg_solve(pdg_ctx *ctx, const double *rhs, double *x, double tol, int32_t maxit,
+                     pdg_solve_info *info);
+
+/* One time step of eq. (4) in place on caller-owned device buffers:
+ * ionic update, ion term, right-hand side, PCG from x0 = U^k;
+ * u: U^k -> U^(k+1); u_prev: U^(k-1) -> U^k; ions: Y^k -> Y^(k+1);
+ * f_ext nullable.  Synchronises the stream. */
+pdg_status pdg_step(pdg_ctx *ctx, double *u, double *u_prev, double *ions, const double *f_ext,
+                    double tol, int32_t maxit, pdg_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDG_H */

@@ -1,0 +1,92 @@
+// Internal declarations of libpdg: host context, setup routines and kernel
+// launchers.  Not part of the ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pdg.h"
+
+namespace pdg {
+
+struct Error : std::runtime_error {
+    pdg_status code;
+    Error(pdg_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+constexpr int kTile = 64;           // dense inverse tile edge
+constexpr int kMaxLocalDofs = 6144; // largest subdomain handled by the Schwarz kernel
+constexpr int kIonicParams = 24;
+constexpr int kStates = 5;
+
+// ---- host FEM (fem.cpp) ----------------------------------------------------
+int n_basis(int dim, int p);
+void multi_indices(int dim, int p, std::vector<int> &alpha);  // [nd][3] (unused dims 0)
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w);
+// values (and derivatives) of the modal basis at reference point xi in [-1,1]^dim
+void basis_eval(int dim, int p, const int *alpha, int nd, const double *xi, const double *ext,
+                double *phi, double *dphi /* [nd][dim] or null */);
+double lambda_max_sym(int dim, const double *S);
+
+struct Mesh {
+    int dim = 0, p = 0, nd = 0;
+    int64_t n_elem = 0, n_facet = 0;
+    std::vector<int64_t> cell_ptr, facet_elem;
+    std::vector<double> cell_geom, facet_geom, facet_normal, sigma;
+    std::vector<int> alpha;          // [nd][3]
+    std::vector<double> lo, hi, hK;  // bbox [n_elem][dim], diameter
+    // element quadrature in bbox reference coordinates
+    std::vector<int64_t> qp_ptr;     // [n_elem+1]
+    std::vector<double> qp_xi;       // [nq][dim]
+    std::vector<double> qp_w;        // [nq]
+    std::vector<double> norm;        // [n_elem][nd]: prod_j sqrt((2a_j+1)/ext_j)
+};
+
+struct Bsr {
+    int64_t n_rows = 0, nnzb = 0;
+    int nd = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;  // [nnzb][nd][nd]
+};
+
+void build_mesh(Mesh &m, const pdg_mesh *in, int p);
+// Mass blocks M [n_elem][nd][nd] and K = c M + 1/2 A in BSR.
+void assemble(const Mesh &m, double c, double eta0, std::vector<double> &M, Bsr &K);
+void element_inverse(int n, const double *A, double *Ainv);  // small SPD inverse (FP64)
+
+// ---- dense SPD inversion and Schwarz setup (schwarz_setup.cpp) -------------
+// In-place inverse of a dense SPD matrix (row-major n x n).  Throws ENOTSPD.
+void spd_inverse(int64_t n, double *A);
+
+struct DenseSys {
+    int64_t n = 0;          // true size
+    int64_t nt = 0;         // tiles per edge
+    int64_t tile_off = 0;   // offset (in tiles) into the tile store
+};
+
+struct Precond {
+    int n_sub = 0, n_coarse = 0, q = 0, nq0 = 0;
+    int local_prec = PDG_F64, coarse_prec = PDG_F64;
+    std::vector<int32_t> sub_ptr, sub_elems;       // CSR of elements per subdomain
+    std::vector<int32_t> coarse_ptr, coarse_elems; // CSR of elements per coarse element
+    std::vector<int32_t> elem_coarse;
+    std::vector<DenseSys> sys;                     // n_sub local systems (+1 coarse last)
+    std::vector<double> inv64;                     // FP64 inverse tiles (all systems)
+    int64_t n_tiles = 0;
+    std::vector<double> P;                         // [n_elem][nd][nq0]
+    std::vector<double> K0;                        // [N0][N0]
+    int64_t N0 = 0;
+    // work items of the Schwarz kernel: (system, row tile), longest first
+    std::vector<int32_t> item_sys, item_row;
+    std::vector<double> local_inv_dense_cache;     // unused; kept empty
+};
+
+void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
+                   const pdg_precond_desc *d, Precond &pc, int n_threads);
+void dense_inverse_of_system(const Precond &pc, int s, std::vector<double> &out);
+
+}  // namespace pdg

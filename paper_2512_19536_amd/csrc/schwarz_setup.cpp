@@ -1,0 +1,315 @@
+// Host-side setup of the two-level additive Schwarz preconditioner of
+// Section 4, eq. (5):
+//   local level:  K_i = principal submatrix of K on the dofs of subdomain i;
+//   coarse level: P = exact L^2 injection of P^q on each coarse agglomerate
+//                 (same modal basis on the agglomerate's bounding box),
+//                 K_0 = P^T K P.
+// Every K_i and K_0 is inverted densely in FP64 (Cholesky, then the inverse of
+// the factor) and stored as packed lower-triangular 64 x 64 tiles, the layout
+// the Schwarz-apply kernel streams.  Setup work, not part of the hot path.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "pdg_internal.h"
+
+namespace pdg {
+
+template <class F>
+static void parallel_for(int64_t n, F f, int n_threads) {
+    if (n_threads <= 0) n_threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    n_threads = (int)std::min<int64_t>(n_threads, std::max<int64_t>(1, n));
+    std::atomic<int64_t> next{0};
+    std::atomic<int> failed{0};
+    Error first(PDG_OK, "");
+    auto worker = [&]() {
+        for (;;) {
+            int64_t i = next.fetch_add(1);
+            if (i >= n || failed.load()) break;
+            try {
+                f(i);
+            } catch (Error &e) {
+                if (failed.exchange(1) == 0) first = e;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < n_threads; ++t) th.emplace_back(worker);
+    worker();
+    for (auto &t : th) t.join();
+    if (failed.load()) throw first;
+}
+
+static inline double dot(const double *a, const double *b, int64_t n) {
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int64_t k = 0;
+    for (; k + 4 <= n; k += 4) {
+        s0 += a[k] * b[k];
+        s1 += a[k + 1] * b[k + 1];
+        s2 += a[k + 2] * b[k + 2];
+        s3 += a[k + 3] * b[k + 3];
+    }
+    for (; k < n; ++k) s0 += a[k] * b[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// A (row-major, SPD) -> A^{-1}.  Row-oriented Cholesky A = L L^T, then the
+// rows of W^T = (L^{-1})^T by forward substitution, then A^{-1} = W^T W.
+void spd_inverse(int64_t n, double *A) {
+    std::vector<double> L(n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        double *Li = &L[i * n];
+        for (int64_t j = 0; j <= i; ++j) {
+            const double *Lj = &L[j * n];
+            double s = A[i * n + j] - dot(Li, Lj, j);
+            if (i == j) {
+                if (!(s > 0.0) || !std::isfinite(s))
+                    throw Error(PDG_ENOTSPD, "Cholesky pivot <= 0 (matrix not SPD)");
+                Li[i] = std::sqrt(s);
+            } else {
+                Li[j] = s / Lj[j];
+            }
+        }
+    }
+    // Wt[j][k] = (L^{-1})[k][j], k >= j: solve L w = e_j
+    std::vector<double> Wt(n * n, 0.0);
+    std::vector<double> w(n);
+    for (int64_t j = 0; j < n; ++j) {
+        std::fill(w.begin(), w.end(), 0.0);
+        w[j] = 1.0 / L[j * n + j];
+        for (int64_t k = j + 1; k < n; ++k) {
+            const double *Lk = &L[k * n];
+            w[k] = -dot(Lk + j, &w[j], k - j) / Lk[k];
+        }
+        std::copy(w.begin() + j, w.end(), &Wt[j * n + j]);
+    }
+    // A^{-1}[i][j] = sum_{k >= max(i,j)} Wt[i][k] Wt[j][k]
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            double s = dot(&Wt[i * n + i], &Wt[j * n + i], n - i);
+            A[i * n + j] = s;
+            A[j * n + i] = s;
+        }
+}
+
+static void store_tiles(const double *D, int64_t n, double *tiles) {
+    const int64_t nt = (n + kTile - 1) / kTile;
+    for (int64_t I = 0; I < nt; ++I)
+        for (int64_t J = 0; J <= I; ++J) {
+            double *t = tiles + (I * (I + 1) / 2 + J) * kTile * kTile;
+            for (int r = 0; r < kTile; ++r)
+                for (int c = 0; c < kTile; ++c) {
+                    int64_t gr = I * kTile + r, gc = J * kTile + c;
+                    t[r * kTile + c] = (gr < n && gc < n) ? D[gr * n + gc] : 0.0;
+                }
+        }
+}
+
+void dense_inverse_of_system(const Precond &pc, int s, std::vector<double> &out) {
+    const DenseSys &S = pc.sys[s];
+    out.assign(S.n * S.n, 0.0);
+    for (int64_t I = 0; I < S.nt; ++I)
+        for (int64_t J = 0; J <= I; ++J) {
+            const double *t = &pc.inv64[(S.tile_off + I * (I + 1) / 2 + J) * kTile * kTile];
+            for (int r = 0; r < kTile; ++r)
+                for (int c = 0; c < kTile; ++c) {
+                    int64_t gr = I * kTile + r, gc = J * kTile + c;
+                    if (gr < S.n && gc < S.n) {
+                        out[gr * S.n + gc] = t[r * kTile + c];
+                        out[gc * S.n + gr] = t[r * kTile + c];
+                    }
+                }
+        }
+}
+
+void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
+                   const pdg_precond_desc *d, Precond &pc, int n_threads) {
+    if (!d || d->n_sub < 1 || !d->elem_sub) throw Error(PDG_EINVAL, "bad preconditioner descriptor");
+    const int64_t n = m.n_elem;
+    const int nd = m.nd, dim = m.dim;
+    for (int pr : {d->local_prec, d->coarse_prec})
+        if (pr != PDG_F64 && pr != PDG_F32 && pr != PDG_BF16) throw Error(PDG_EINVAL, "bad precision");
+    if (d->coarse_prec == PDG_BF16) throw Error(PDG_EINVAL, "coarse precision must be F64 or F32");
+    if (d->coarse_q < 0 || d->coarse_q > m.p) throw Error(PDG_EINVAL, "coarse_q must be in 0..p");
+    pc = Precond();
+    pc.n_sub = d->n_sub;
+    pc.local_prec = d->local_prec;
+    pc.coarse_prec = d->coarse_prec;
+    pc.q = d->coarse_q;
+
+    // subdomain CSR (elements in ascending order inside a subdomain)
+    std::vector<int32_t> cnt(pc.n_sub, 0);
+    for (int64_t e = 0; e < n; ++e) {
+        int s = d->elem_sub[e];
+        if (s < 0 || s >= pc.n_sub) throw Error(PDG_EINVAL, "elem_sub label out of range");
+        cnt[s]++;
+    }
+    pc.sub_ptr.assign(pc.n_sub + 1, 0);
+    for (int s = 0; s < pc.n_sub; ++s) {
+        if (cnt[s] == 0) throw Error(PDG_EINVAL, "empty subdomain");
+        if ((int64_t)cnt[s] * nd > kMaxLocalDofs) throw Error(PDG_EINVAL, "subdomain exceeds 6144 dofs");
+        pc.sub_ptr[s + 1] = pc.sub_ptr[s] + cnt[s];
+    }
+    pc.sub_elems.assign(n, 0);
+    std::vector<int32_t> fill(pc.sub_ptr.begin(), pc.sub_ptr.end() - 1);
+    std::vector<int32_t> pos(n);
+    for (int64_t e = 0; e < n; ++e) {
+        int s = d->elem_sub[e];
+        pos[e] = fill[s] - pc.sub_ptr[s];
+        pc.sub_elems[fill[s]++] = (int32_t)e;
+    }
+
+    // system table: locals then (optionally) the coarse system
+    const bool coarse = pc.q > 0;
+    pc.sys.resize(pc.n_sub + (coarse ? 1 : 0));
+    int64_t toff = 0;
+    for (int s = 0; s < pc.n_sub; ++s) {
+        DenseSys &S = pc.sys[s];
+        S.n = (int64_t)cnt[s] * nd;
+        S.nt = (S.n + kTile - 1) / kTile;
+        S.tile_off = toff;
+        toff += S.nt * (S.nt + 1) / 2;
+    }
+
+    // coarse space
+    std::vector<double> K0;
+    if (coarse) {
+        const int32_t *ec = d->elem_coarse ? d->elem_coarse : d->elem_sub;
+        pc.n_coarse = d->elem_coarse ? d->n_coarse : d->n_sub;
+        if (pc.n_coarse < 1) throw Error(PDG_EINVAL, "n_coarse < 1");
+        pc.elem_coarse.assign(ec, ec + n);
+        std::vector<int32_t> cc(pc.n_coarse, 0);
+        for (int64_t e = 0; e < n; ++e) {
+            if (ec[e] < 0 || ec[e] >= pc.n_coarse) throw Error(PDG_EINVAL, "elem_coarse label out of range");
+            cc[ec[e]]++;
+        }
+        pc.coarse_ptr.assign(pc.n_coarse + 1, 0);
+        for (int c = 0; c < pc.n_coarse; ++c) {
+            if (cc[c] == 0) throw Error(PDG_EINVAL, "empty coarse element");
+            pc.coarse_ptr[c + 1] = pc.coarse_ptr[c] + cc[c];
+        }
+        pc.coarse_elems.assign(n, 0);
+        std::vector<int32_t> cf(pc.coarse_ptr.begin(), pc.coarse_ptr.end() - 1);
+        for (int64_t e = 0; e < n; ++e) pc.coarse_elems[cf[ec[e]]++] = (int32_t)e;
+        // coarse bounding boxes
+        std::vector<double> clo(pc.n_coarse * dim, 1e300), chi(pc.n_coarse * dim, -1e300);
+        for (int64_t e = 0; e < n; ++e)
+            for (int k = 0; k < dim; ++k) {
+                clo[ec[e] * dim + k] = std::min(clo[ec[e] * dim + k], m.lo[e * dim + k]);
+                chi[ec[e] * dim + k] = std::max(chi[ec[e] * dim + k], m.hi[e * dim + k]);
+            }
+        std::vector<int> alpha0;
+        multi_indices(dim, pc.q, alpha0);
+        pc.nq0 = n_basis(dim, pc.q);
+        const int nq0 = pc.nq0;
+        pc.P.assign(n * nd * nq0, 0.0);
+        parallel_for(n, [&](int64_t e) {
+            const double *lo = &m.lo[e * dim], *hi = &m.hi[e * dim];
+            double ext[3], cext[3];
+            const int c = ec[e];
+            for (int k = 0; k < dim; ++k) { ext[k] = hi[k] - lo[k]; cext[k] = chi[c * dim + k] - clo[c * dim + k]; }
+            std::vector<double> G(nd * nq0, 0.0), phi(nd), psi(nq0), Minv(nd * nd);
+            for (int64_t q = m.qp_ptr[e]; q < m.qp_ptr[e + 1]; ++q) {
+                const double *xi = &m.qp_xi[q * dim];
+                double cxi[3];
+                for (int k = 0; k < dim; ++k) {
+                    double x = lo[k] + 0.5 * (xi[k] + 1.0) * ext[k];
+                    cxi[k] = 2.0 * (x - clo[c * dim + k]) / cext[k] - 1.0;
+                }
+                basis_eval(dim, m.p, m.alpha.data(), nd, xi, ext, phi.data(), nullptr);
+                basis_eval(dim, pc.q, alpha0.data(), nq0, cxi, cext, psi.data(), nullptr);
+                for (int i = 0; i < nd; ++i)
+                    for (int j = 0; j < nq0; ++j) G[i * nq0 + j] += m.qp_w[q] * phi[i] * psi[j];
+            }
+            element_inverse(nd, &Mblk[e * nd * nd], Minv.data());
+            double *PK = &pc.P[e * nd * nq0];
+            for (int i = 0; i < nd; ++i)
+                for (int j = 0; j < nq0; ++j) {
+                    double s = 0;
+                    for (int k = 0; k < nd; ++k) s += Minv[i * nd + k] * G[k * nq0 + j];
+                    PK[i * nq0 + j] = s;
+                }
+        }, n_threads);
+        // K0 = P^T K P, accumulated row-block by row-block of K
+        pc.N0 = (int64_t)pc.n_coarse * nq0;
+        const int64_t N0 = pc.N0;
+        K0.assign(N0 * N0, 0.0);
+        std::vector<double> KP(nd * nq0);
+        for (int64_t e = 0; e < n; ++e) {
+            const double *Pe = &pc.P[e * nd * nq0];
+            for (int64_t k = K.row_ptr[e]; k < K.row_ptr[e + 1]; ++k) {
+                const int64_t o = K.col[k];
+                const double *Kb = &K.val[k * nd * nd];
+                const double *Po = &pc.P[o * nd * nq0];
+                for (int i = 0; i < nd; ++i)
+                    for (int j = 0; j < nq0; ++j) {
+                        double s = 0;
+                        for (int t = 0; t < nd; ++t) s += Kb[i * nd + t] * Po[t * nq0 + j];
+                        KP[i * nq0 + j] = s;
+                    }
+                const int64_t r0 = (int64_t)ec[e] * nq0, c0 = (int64_t)ec[o] * nq0;
+                for (int a = 0; a < nq0; ++a)
+                    for (int b = 0; b < nq0; ++b) {
+                        double s = 0;
+                        for (int i = 0; i < nd; ++i) s += Pe[i * nq0 + a] * KP[i * nq0 + b];
+                        K0[(r0 + a) * N0 + c0 + b] += s;
+                    }
+            }
+        }
+        for (int64_t i = 0; i < N0; ++i)
+            for (int64_t j = 0; j < i; ++j) {
+                double s = 0.5 * (K0[i * N0 + j] + K0[j * N0 + i]);
+                K0[i * N0 + j] = K0[j * N0 + i] = s;
+            }
+        pc.K0 = K0;
+        DenseSys &S = pc.sys[pc.n_sub];
+        S.n = N0;
+        S.nt = (N0 + kTile - 1) / kTile;
+        S.tile_off = toff;
+        toff += S.nt * (S.nt + 1) / 2;
+    }
+    pc.n_tiles = toff;
+    pc.inv64.assign(pc.n_tiles * kTile * kTile, 0.0);
+
+    // local inverses (parallel over subdomains)
+    parallel_for(pc.n_sub, [&](int64_t s) {
+        const int64_t ni = pc.sys[s].n;
+        std::vector<double> D(ni * ni, 0.0);
+        for (int32_t le = 0; le < cnt[s]; ++le) {
+            const int32_t e = pc.sub_elems[pc.sub_ptr[s] + le];
+            for (int64_t k = K.row_ptr[e]; k < K.row_ptr[e + 1]; ++k) {
+                const int32_t o = K.col[k];
+                if (d->elem_sub[o] != s) continue;
+                const int32_t lo = pos[o];
+                const double *Kb = &K.val[k * nd * nd];
+                for (int i = 0; i < nd; ++i)
+                    for (int j = 0; j < nd; ++j) D[(int64_t)(le * nd + i) * ni + lo * nd + j] = Kb[i * nd + j];
+            }
+        }
+        spd_inverse(ni, D.data());
+        store_tiles(D.data(), ni, &pc.inv64[pc.sys[s].tile_off * kTile * kTile]);
+    }, n_threads);
+    if (coarse) {
+        spd_inverse(pc.N0, K0.data());
+        store_tiles(K0.data(), pc.N0, &pc.inv64[pc.sys[pc.n_sub].tile_off * kTile * kTile]);
+    }
+
+    // work items (system, row tile), longest rows first (LPT order)
+    std::vector<std::pair<int64_t, int64_t>> items;
+    for (size_t s = 0; s < pc.sys.size(); ++s)
+        for (int64_t I = 0; I < pc.sys[s].nt; ++I) items.push_back({(int64_t)s, I});
+    std::stable_sort(items.begin(), items.end(), [&](const auto &a, const auto &b) {
+        return pc.sys[a.first].nt > pc.sys[b.first].nt;
+    });
+    pc.item_sys.clear();
+    pc.item_row.clear();
+    for (auto &it : items) {
+        pc.item_sys.push_back((int32_t)it.first);
+        pc.item_row.push_back((int32_t)it.second);
+    }
+}
+
+}  // namespace pdg
