@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
     ap.add_argument("--local-prec", default=None, choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--item-kb", type=int, default=None, help="Schwarz work-item size (KiB of tiles)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=1024)
     args = ap.parse_args()
@@ -110,7 +111,8 @@ def main():
     log(f"[bench] workload {pr.name}: {pr.n_elem} elements, p={pr.p}, {pr.n_dof} dofs, "
         f"{pr.n_sub} subdomains; inputs {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    ctx = from_problem(pr, device=dev)
+    opts = {_lib.PDG_OPT_SCHWARZ_ITEM_KB: args.item_kb} if args.item_kb else None
+    ctx = from_problem(pr, device=dev, options=opts)
     torch.cuda.synchronize()
     log(f"[bench] library setup (assembly, Schwarz inverses, upload) {time.perf_counter() - t0:.1f} s")
     U, Up, Y = initial_state(ctx, pr)

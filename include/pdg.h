@@ -176,7 +176,9 @@ pdg_status pdg_bind_workspace(pdg_ctx *ctx, void *dev_ptr, size_t bytes);
 typedef enum {
     PDG_OPT_TRUE_RESIDUAL = 1,  /* 1: pdg_solve/pdg_step compute ||b - Kx||/||b|| (one extra SpMV) */
     PDG_OPT_CHUNK = 2,          /* PCG iterations launched between host convergence polls (>= 1) */
-    PDG_OPT_KERNEL_TIMING = 3   /* 1: time every Schwarz-apply launch with HIP events */
+    PDG_OPT_KERNEL_TIMING = 3,  /* 1: time every Schwarz-apply launch with HIP events */
+    PDG_OPT_SCHWARZ_ITEM_KB = 4 /* target tile bytes (KiB) per Schwarz work item, 32..8192,
+                                   default 256; set before pdg_setup_preconditioner */
 } pdg_option;
 pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 

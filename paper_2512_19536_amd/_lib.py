@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpdg.so")
 PDG_OK, PDG_EINVAL, PDG_ENOMEM, PDG_EHIP, PDG_ENOTSPD, PDG_ENOCONV, PDG_EBREAKDOWN, PDG_ENONFINITE, PDG_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PDG_F64, PDG_F32, PDG_BF16 = 0, 1, 2
-PDG_OPT_TRUE_RESIDUAL, PDG_OPT_CHUNK, PDG_OPT_KERNEL_TIMING = 1, 2, 3
+PDG_OPT_TRUE_RESIDUAL, PDG_OPT_CHUNK, PDG_OPT_KERNEL_TIMING, PDG_OPT_SCHWARZ_ITEM_KB = 1, 2, 3, 4
 PRECISIONS = {"f64": PDG_F64, "f32": PDG_F32, "bf16": PDG_BF16}
 
 #: every symbol declared in include/pdg.h

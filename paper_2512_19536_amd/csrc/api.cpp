@@ -60,7 +60,7 @@ struct pdg_ctx {
     std::string err;
     int n_threads = 0;
     // options
-    int true_resid = 0, chunk = 4, timing = 0;
+    int true_resid = 0, chunk = 4, timing = 0, item_kb = 256;
     int prev_iters = 0;
     // host data
     Mesh mesh;
@@ -70,7 +70,11 @@ struct pdg_ctx {
     std::vector<double> ionic;
     bool has_ionic = false;
     Precond pc;
-    std::vector<int32_t> grp_ptr, grp_elems;  // update groups
+    std::vector<int32_t> grp_ptr, grp_elems;  // update chunks (element runs inside one coarse element)
+    std::vector<int32_t> cchunk_ptr;          // [n_coarse+1] chunks of each coarse element
+    // Schwarz work items
+    std::vector<int32_t> it_sys, it_row, it_j0, it_nj, it_rt, rt_item0;
+    int max_nj = 1;
     // group-ELL matrix (host staging)
     int G = 1;
     int64_t n_groups = 0, n_slots = 0;
@@ -83,17 +87,26 @@ struct pdg_ctx {
     size_t ws_bytes = 0;
     DevMatrix dA{};
     DevScalars *sc = nullptr, *sc_apply = nullptr, *sc_host = nullptr;
-    RedSlot red[4]{};
     int64_t *d_qp_ptr = nullptr;
     double *d_qp_xi = nullptr, *d_qp_w = nullptr, *d_norm = nullptr, *d_minv = nullptr, *d_prm = nullptr;
-    int32_t *d_sub_ptr = nullptr, *d_sub_elems = nullptr, *d_item_sys = nullptr, *d_item_row = nullptr;
+    int32_t *d_sub_ptr = nullptr, *d_sub_elems = nullptr;
     int32_t *d_sys_n = nullptr, *d_sys_nt = nullptr, *d_elem_coarse = nullptr;
-    int32_t *d_grp_ptr = nullptr, *d_grp_elems = nullptr;
-    int64_t *d_sys_toff = nullptr;
+    int32_t *d_grp_ptr = nullptr, *d_grp_elems = nullptr, *d_cchunk_ptr = nullptr;
+    int32_t *d_it_sys = nullptr, *d_it_row = nullptr, *d_it_j0 = nullptr, *d_it_nj = nullptr, *d_it_rt = nullptr,
+            *d_rt_item0 = nullptr;
+    int32_t *d_dof_rt = nullptr;
+    double *d_part = nullptr, *d_r0part = nullptr, *d_itemdot = nullptr, *d_spart = nullptr, *d_rrpart = nullptr;
+    std::vector<int32_t> dof_rt;
+    int coarse_rt0 = -1;
+    int64_t *d_sys_toff = nullptr, *d_sys_dof0 = nullptr, *d_sys_cbase = nullptr, *d_rt_cbase = nullptr;
+    int32_t *d_rt_k = nullptr, *d_rt_nt = nullptr;
+    double *d_colpart = nullptr;
+    std::vector<int32_t> rt_k, rt_nt;
+    std::vector<int64_t> rt_cbase;
     void *d_tiles_local = nullptr, *d_tiles_coarse = nullptr;
     double *d_P = nullptr;
     double *v_r = nullptr, *v_z = nullptr, *v_p = nullptr, *v_q = nullptr, *v_I = nullptr, *v_t = nullptr,
-           *v_b = nullptr, *v_r0 = nullptr, *v_z0 = nullptr;
+           *v_b = nullptr, *v_z0 = nullptr;
     int max_sys_n = 0;
     int64_t schwarz_bytes = 0;
     // kernel timing
@@ -184,8 +197,9 @@ size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32
 
 enum WsItem {
     W_GROWS, W_GSLOT, W_GCOL, W_GVAL, W_MASS, W_MINV, W_QPPTR, W_QPXI, W_QPW, W_NORM, W_PRM,
-    W_SUBPTR, W_SUBEL, W_ISYS, W_IROW, W_SYSN, W_SYSNT, W_SYSTOFF, W_TLOC, W_TCOA, W_P, W_ECOA,
-    W_GRPPTR, W_GRPEL, W_R, W_Z, W_PV, W_Q, W_I, W_T, W_B, W_R0, W_Z0, W_SC, W_SCA, W_PART, W_CNT, W_COUNT
+    W_SUBPTR, W_SUBEL, W_ITSYS, W_ITROW, W_ITJ0, W_ITNJ, W_ITRT, W_RTIT0, W_DOFRT, W_ITDOT, W_SPART,
+    W_SYSN, W_SYSNT, W_SYSTOFF, W_SYSDOF0, W_SYSCB, W_RTK, W_RTNT, W_RTCB, W_COLP, W_TLOC, W_TCOA, W_P, W_ECOA, W_GRPPTR, W_GRPEL, W_CCHUNK,
+    W_R, W_Z, W_PV, W_Q, W_I, W_T, W_B, W_R0P, W_Z0, W_SC, W_SCA, W_PART, W_RRPART, W_COUNT
 };
 
 void plan_layout(pdg_ctx *c) {
@@ -197,7 +211,8 @@ void plan_layout(pdg_ctx *c) {
     if (pc.q > 0) coarse_tiles = pc.sys[pc.n_sub].nt * (pc.sys[pc.n_sub].nt + 1) / 2;
     const int64_t N0 = std::max<int64_t>(1, pc.N0);
     int64_t max_grid = std::max<int64_t>({(int64_t)spmv_blocks(DevMatrix{(int)nd, c->G, n, c->n_groups}),
-                                          (int64_t)c->grp_ptr.size(), (int64_t)pc.item_sys.size(), 1});
+                                          (int64_t)c->grp_ptr.size(), 1});
+    const int64_t n_items = (int64_t)c->it_sys.size(), n_rt = (int64_t)c->rt_item0.size() - 1;
     Layout &L = c->lay;
     L = Layout();
     L.add(c->grp_rows.size() * 4);
@@ -213,24 +228,34 @@ void plan_layout(pdg_ctx *c) {
     L.add(kIonicParams * 8);
     L.add(pc.sub_ptr.size() * 4);
     L.add(pc.sub_elems.size() * 4);
-    L.add(pc.item_sys.size() * 4);
-    L.add(pc.item_row.size() * 4);
+    for (int k = 0; k < 5; ++k) L.add(n_items * 4);   // item sys/row/j0/nj/rt
+    L.add((n_rt + 1) * 4);
+    L.add(N * 4);
+    L.add(n_items * 8);
+    L.add(n_items * kTile * 8);
     L.add(n_sys * 4);
     L.add(n_sys * 4);
     L.add(n_sys * 8);
+    L.add(n_sys * 8);
+    L.add(n_sys * 8);
+    L.add(n_rt * 4);
+    L.add(n_rt * 4);
+    L.add(n_rt * 8);
+    L.add((local_tiles + coarse_tiles) * kTile * 8);
     L.add(local_tiles * kTile * kTile * tile_elem_bytes(pc.local_prec));
     L.add(coarse_tiles * kTile * kTile * tile_elem_bytes(pc.coarse_prec));
     L.add(pc.P.size() * 8);
     L.add(pc.elem_coarse.size() * 4);
     L.add(c->grp_ptr.size() * 4);
     L.add(c->grp_elems.size() * 4);
+    L.add(c->cchunk_ptr.size() * 4);
     for (int k = 0; k < 7; ++k) L.add(N * 8);  // r z p q I t b
-    L.add(N0 * 8);
+    L.add(std::max<int64_t>(1, (int64_t)c->grp_ptr.size() * std::max(pc.nq0, 1)) * 8);  // r0 shares per chunk
     L.add(N0 * 8);
     L.add(sizeof(DevScalars));
     L.add(sizeof(DevScalars));
-    L.add(4 * max_grid * 2 * 8);
-    L.add(4 * 64);
+    L.add(std::max<int64_t>(1, c->n_groups) * 2 * 8);   // SpMV partials
+    L.add(std::max<int64_t>(1, (int64_t)c->grp_ptr.size()) * 8);  // update partials
 }
 
 template <class T>
@@ -256,25 +281,31 @@ pdg_status map_status(int st) {
 
 int store_kind(int prec) { return prec == PDG_F64 ? STORE_F64 : (prec == PDG_F32 ? STORE_F32 : STORE_BF16); }
 
-SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, double *z, DevScalars *sc) {
+SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) {
     SchwarzArgs a{};
     a.mode = mode;
     a.nd = c->mesh.nd;
     a.n_sub = c->pc.n_sub;
-    a.item_sys = c->d_item_sys;
-    a.item_row = c->d_item_row;
+    a.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
+    a.item_sys = c->d_it_sys;
+    a.item_row = c->d_it_row;
+    a.item_j0 = c->d_it_j0;
+    a.item_nj = c->d_it_nj;
+    a.part = c->d_part;
+    a.itemdot = c->d_itemdot;
     a.sys_n = c->d_sys_n;
     a.sys_nt = c->d_sys_nt;
     a.sys_toff = c->d_sys_toff;
+    a.sys_dof0 = c->d_sys_dof0;
+    a.sys_cbase = c->d_sys_cbase;
+    a.colpart = c->d_colpart;
     a.tiles_local = c->d_tiles_local;
     a.tiles_coarse = c->d_tiles_coarse;
     a.sub_ptr = c->d_sub_ptr;
     a.sub_elems = c->d_sub_elems;
+    a.cchunk_ptr = c->d_cchunk_ptr;
     a.r = r;
-    a.r0 = c->v_r0;
-    a.z = z;
-    a.z0 = c->v_z0;
-    a.red = c->red[2];
+    a.r0part = c->d_r0part;
     a.sc = sc;
     return a;
 }
@@ -292,8 +323,8 @@ void launch_schwarz_timed(pdg_ctx *c, const SchwarzArgs &a) {
         e1 = c->ev_pool[c->ev_used].second;
         HIPCHK(hipEventRecord(e0, c->stream));
     }
-    HIPCHK(launch_schwarz(a, (int)c->pc.item_sys.size(), store_kind(c->pc.local_prec),
-                          store_kind(c->pc.coarse_prec), c->max_sys_n, c->stream));
+    HIPCHK(launch_schwarz(a, (int)c->it_sys.size(), store_kind(c->pc.local_prec),
+                          store_kind(c->pc.coarse_prec), c->max_nj, c->stream));
     if (c->timing) {
         HIPCHK(hipEventRecord(e1, c->stream));
         c->ev_used++;
@@ -327,22 +358,37 @@ UpdateArgs update_args(pdg_ctx *c, int init, int iter, double *x, double *r, Dev
     u.p = c->v_p;
     u.q = c->v_q;
     u.P = c->d_P;
-    u.r0 = c->v_r0;
-    u.red = c->red[1];
+    u.r0part = c->d_r0part;
+    u.pqpart = c->d_spart;
+    u.n_pq = (int)c->n_groups;
+    u.rrpart = c->d_rrpart;
     u.sc = sc;
     return u;
 }
 
-PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
+PupdateArgs pupdate_args(pdg_ctx *c, int mode, int iter, double *out, DevScalars *sc) {
     PupdateArgs p{};
     p.mode = mode;
+    p.iter = iter;
     p.nd = c->mesh.nd;
     p.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
     p.n_elem = c->mesh.n_elem;
-    p.z = c->v_z;
-    p.z0 = c->v_z0;
     p.P = c->d_P;
     p.elem_coarse = c->d_elem_coarse;
+    p.dof_rt = c->d_dof_rt;
+    p.rt_item0 = c->d_rt_item0;
+    p.rt_k = c->d_rt_k;
+    p.rt_nt = c->d_rt_nt;
+    p.rt_cbase = c->d_rt_cbase;
+    p.colpart = c->d_colpart;
+    p.coarse_rt0 = c->coarse_rt0;
+    p.part = c->d_part;
+    p.itemdot = c->d_itemdot;
+    p.n_items = (int)c->it_sys.size();
+    p.rrpart = c->d_rrpart;
+    p.n_rr = (int)c->grp_ptr.size() - 1;
+    p.bbpart = c->d_spart;
+    p.n_bb = (int)c->n_groups;
     p.p = out;
     p.sc = sc;
     return p;
@@ -359,9 +405,8 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
     HIPCHK(launch_status_reset(sc, tol * tol, maxit, 0, s));
     SpmvArgs a{};
     a.x = x;
-    a.red = c->red[0];
+    a.part = c->d_spart;
     a.sc = sc;
-    a.bb_out = &sc->bb;
     if (step_mode) {
         a.mode = SPMV_STEP;
         a.y = c->v_r;
@@ -383,8 +428,8 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
     HIPCHK(launch_spmv(c->dA, a, s));
     HIPCHK(launch_update(update_args(c, 1, 0, x, c->v_r, sc), s));
     c->ev_used = 0;
-    launch_schwarz_timed(c, schwarz_args(c, 1, c->v_r, c->v_z, sc));
-    HIPCHK(launch_pupdate(pupdate_args(c, 1, c->v_p, sc), s));
+    launch_schwarz_timed(c, schwarz_args(c, 1, c->v_r, sc));
+    HIPCHK(launch_pupdate(pupdate_args(c, 1, 0, c->v_p, sc), s));
     int j = 1;
     int chunk = c->prev_iters > 0 ? std::max(1, c->prev_iters) : c->chunk;
     bool done = false;
@@ -394,12 +439,12 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
             q.mode = SPMV_PQ;
             q.x = c->v_p;
             q.y = c->v_q;
-            q.red = c->red[0];
+            q.part = c->d_spart;
             q.sc = sc;
             HIPCHK(launch_spmv(c->dA, q, s));
             HIPCHK(launch_update(update_args(c, 0, j, x, c->v_r, sc), s));
-            launch_schwarz_timed(c, schwarz_args(c, 2, c->v_r, c->v_z, sc));
-            HIPCHK(launch_pupdate(pupdate_args(c, 2, c->v_p, sc), s));
+            launch_schwarz_timed(c, schwarz_args(c, 2, c->v_r, sc));
+            HIPCHK(launch_pupdate(pupdate_args(c, 2, j, c->v_p, sc), s));
         }
         HIPCHK(hipMemcpyAsync(c->sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -407,7 +452,9 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
         chunk = c->chunk;
     }
     const DevScalars h = *c->sc_host;
-    harvest_timing(c, (size_t)h.iters);  // launches that did work: init + iterations 1..iters-1
+    // Schwarz launches that did work: init + iterations 1..iters (convergence is
+    // detected after the Schwarz kernel of the converged iteration)
+    harvest_timing(c, (size_t)h.iters + 1);
     if (h.status == ST_ZERO_RHS) HIPCHK(launch_zero(x, c->mesh.n_elem * c->mesh.nd, s));
     pdg_solve_info out{};
     out.iters = h.iters;
@@ -420,11 +467,10 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
         t.x = x;
         t.b = step_mode ? c->v_b : b;
         t.y = c->v_t;
-        t.red = c->red[3];
+        t.part = c->d_spart;
         t.sc = sc;
-        t.bb_out = nullptr;
-        t.rr_out = &sc->tr;
         HIPCHK(launch_spmv(c->dA, t, s));
+        HIPCHK(launch_sum_partials(c->d_spart, (int)c->n_groups, 1, &sc->tr, s));
         HIPCHK(hipMemcpyAsync(c->sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         out.true_relres = std::sqrt(c->sc_host->tr / h.bb);
@@ -570,18 +616,74 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         if (d && d->coarse_q > 1) throw Error(PDG_EINVAL, "coarse_q must be 0 or 1");
         setup_precond(c->mesh, c->K, c->M, d, c->pc, c->n_threads);
         if (c->pc.q > 0 && c->pc.N0 > kMaxLocalDofs) throw Error(PDG_EINVAL, "coarse system exceeds 6144 dofs");
-        // update groups: coarse elements, or chunks of 64 elements without a coarse level
-        c->grp_ptr.clear();
+        // update chunks: runs of at most 32 elements inside one coarse element
+        // (or over the element order without a coarse level)
+        constexpr int kChunk = 32;
+        c->grp_ptr.assign(1, 0);
         c->grp_elems.clear();
+        c->cchunk_ptr.assign(1, 0);
         if (c->pc.q > 0) {
-            c->grp_ptr = c->pc.coarse_ptr;
-            c->grp_elems = c->pc.coarse_elems;
+            for (int cc = 0; cc < c->pc.n_coarse; ++cc) {
+                const int a0 = c->pc.coarse_ptr[cc], a1 = c->pc.coarse_ptr[cc + 1];
+                for (int e = a0; e < a1; e += kChunk) {
+                    for (int k = e; k < std::min(a1, e + kChunk); ++k) c->grp_elems.push_back(c->pc.coarse_elems[k]);
+                    c->grp_ptr.push_back((int32_t)c->grp_elems.size());
+                }
+                c->cchunk_ptr.push_back((int32_t)c->grp_ptr.size() - 1);
+            }
         } else {
             const int64_t n = c->mesh.n_elem;
-            for (int64_t e = 0; e < n; e += 64) c->grp_ptr.push_back((int32_t)e);
-            c->grp_ptr.push_back((int32_t)n);
-            c->grp_elems.resize(n);
-            std::iota(c->grp_elems.begin(), c->grp_elems.end(), 0);
+            for (int64_t e = 0; e < n; e += kChunk) {
+                for (int64_t k = e; k < std::min<int64_t>(n, e + kChunk); ++k) c->grp_elems.push_back((int32_t)k);
+                c->grp_ptr.push_back((int32_t)c->grp_elems.size());
+            }
+        }
+        // Schwarz work items: the stored tiles (I, J <= I) of each packed tile
+        // row, split into runs of ~item_kb KiB
+        c->it_sys.clear(); c->it_row.clear(); c->it_j0.clear(); c->it_nj.clear(); c->it_rt.clear();
+        c->rt_item0.assign(1, 0);
+        c->rt_k.clear(); c->rt_nt.clear(); c->rt_cbase.clear();
+        c->max_nj = 1;
+        int64_t nloc_tiles = 0;
+        for (int sidx = 0; sidx < c->pc.n_sub; ++sidx) nloc_tiles += c->pc.sys[sidx].nt * (c->pc.sys[sidx].nt + 1) / 2;
+        for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx) {
+            const int64_t nt = c->pc.sys[sidx].nt;
+            const int prec = (int)sidx < c->pc.n_sub ? c->pc.local_prec : c->pc.coarse_prec;
+            const int64_t jc = std::max<int64_t>(1, ((int64_t)c->item_kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
+            const int64_t cbase = (int)sidx < c->pc.n_sub ? c->pc.sys[sidx].tile_off : nloc_tiles;
+            for (int64_t I = 0; I < nt; ++I) {
+                const int32_t rt = (int32_t)c->rt_item0.size() - 1;
+                const int64_t ntile = I + 1, nc = (ntile + jc - 1) / jc;
+                for (int64_t k = 0; k < nc; ++k) {
+                    const int64_t j0 = k * ntile / nc, j1 = (k + 1) * ntile / nc;
+                    c->it_sys.push_back((int32_t)sidx);
+                    c->it_row.push_back((int32_t)I);
+                    c->it_j0.push_back((int32_t)j0);
+                    c->it_nj.push_back((int32_t)(j1 - j0));
+                    c->it_rt.push_back(rt);
+                    c->max_nj = std::max<int>(c->max_nj, (int)(j1 - j0));
+                }
+                c->rt_item0.push_back((int32_t)c->it_sys.size());
+                c->rt_k.push_back((int32_t)I);
+                c->rt_nt.push_back((int32_t)nt);
+                c->rt_cbase.push_back(cbase);
+            }
+        }
+        // tile row (and row inside it) of every fine dof, for assembling z
+        {
+            const int nd = c->mesh.nd;
+            c->dof_rt.assign(c->mesh.n_elem * nd, 0);
+            int32_t rt0 = 0;
+            for (int sidx = 0; sidx < c->pc.n_sub; ++sidx) {
+                const int a0 = c->pc.sub_ptr[sidx], a1 = c->pc.sub_ptr[sidx + 1];
+                for (int le = 0; le < a1 - a0; ++le)
+                    for (int i = 0; i < nd; ++i) {
+                        const int pos = le * nd + i;
+                        c->dof_rt[(int64_t)c->pc.sub_elems[a0 + le] * nd + i] = (rt0 + pos / kTile) * kTile + pos % kTile;
+                    }
+                rt0 += (int32_t)c->pc.sys[sidx].nt;
+            }
+            c->coarse_rt0 = c->pc.q > 0 ? rt0 : -1;
         }
         c->max_sys_n = 0;
         for (auto &S : c->pc.sys) c->max_sys_n = std::max<int>(c->max_sys_n, (int)S.n);
@@ -669,8 +771,12 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, W_PRM, prm);
         upload(c, W_SUBPTR, pc.sub_ptr);
         upload(c, W_SUBEL, pc.sub_elems);
-        upload(c, W_ISYS, pc.item_sys);
-        upload(c, W_IROW, pc.item_row);
+        upload(c, W_ITSYS, c->it_sys);
+        upload(c, W_ITROW, c->it_row);
+        upload(c, W_ITJ0, c->it_j0);
+        upload(c, W_ITNJ, c->it_nj);
+        upload(c, W_ITRT, c->it_rt);
+        upload(c, W_RTIT0, c->rt_item0);
         std::vector<int32_t> sys_n, sys_nt;
         std::vector<int64_t> sys_toff;
         for (size_t s = 0; s < pc.sys.size(); ++s) {
@@ -682,6 +788,26 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, W_SYSN, sys_n);
         upload(c, W_SYSNT, sys_nt);
         upload(c, W_SYSTOFF, sys_toff);
+        // subdomains whose elements form one contiguous run gather r directly
+        std::vector<int64_t> sys_dof0(pc.sys.size(), -1);
+        for (int sidx = 0; sidx < pc.n_sub; ++sidx) {
+            const int a0 = pc.sub_ptr[sidx], a1 = pc.sub_ptr[sidx + 1];
+            bool contiguous = true;
+            for (int k = a0 + 1; k < a1 && contiguous; ++k) contiguous = pc.sub_elems[k] == pc.sub_elems[k - 1] + 1;
+            if (contiguous) sys_dof0[sidx] = (int64_t)pc.sub_elems[a0] * nd;
+        }
+        upload(c, W_SYSDOF0, sys_dof0);
+        {
+            int64_t nloc_tiles = 0;
+            for (int sidx = 0; sidx < pc.n_sub; ++sidx) nloc_tiles += pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2;
+            std::vector<int64_t> sys_cbase(pc.sys.size());
+            for (size_t sidx = 0; sidx < pc.sys.size(); ++sidx)
+                sys_cbase[sidx] = (int)sidx < pc.n_sub ? pc.sys[sidx].tile_off : nloc_tiles;
+            upload(c, W_SYSCB, sys_cbase);
+        }
+        upload(c, W_RTK, c->rt_k);
+        upload(c, W_RTNT, c->rt_nt);
+        upload(c, W_RTCB, c->rt_cbase);
         // tiles, converted to the storage precision
         int64_t local_tiles = 0;
         for (int s = 0; s < pc.n_sub; ++s) local_tiles += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
@@ -711,7 +837,8 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, W_ECOA, pc.elem_coarse);
         upload(c, W_GRPPTR, c->grp_ptr);
         upload(c, W_GRPEL, c->grp_elems);
-        HIPCHK(hipMemsetAsync(c->ws + c->lay.items[W_CNT].off, 0, c->lay.items[W_CNT].bytes, c->stream));
+        upload(c, W_CCHUNK, c->cchunk_ptr);
+        upload(c, W_DOFRT, c->dof_rt);
         HIPCHK(hipMemsetAsync(c->ws + c->lay.items[W_SC].off, 0, 2 * 256, c->stream));
         for (int k = W_R; k <= W_Z0; ++k)
             HIPCHK(hipMemsetAsync(c->ws + c->lay.items[k].off, 0, c->lay.items[k].bytes, c->stream));
@@ -734,11 +861,27 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         c->d_prm = wptr<double>(c, W_PRM);
         c->d_sub_ptr = wptr<int32_t>(c, W_SUBPTR);
         c->d_sub_elems = wptr<int32_t>(c, W_SUBEL);
-        c->d_item_sys = wptr<int32_t>(c, W_ISYS);
-        c->d_item_row = wptr<int32_t>(c, W_IROW);
+        c->d_it_sys = wptr<int32_t>(c, W_ITSYS);
+        c->d_it_row = wptr<int32_t>(c, W_ITROW);
+        c->d_it_j0 = wptr<int32_t>(c, W_ITJ0);
+        c->d_it_nj = wptr<int32_t>(c, W_ITNJ);
+        c->d_it_rt = wptr<int32_t>(c, W_ITRT);
+        c->d_rt_item0 = wptr<int32_t>(c, W_RTIT0);
+        c->d_dof_rt = wptr<int32_t>(c, W_DOFRT);
+        c->d_itemdot = wptr<double>(c, W_ITDOT);
+        c->d_spart = wptr<double>(c, W_PART);
+        c->d_rrpart = wptr<double>(c, W_RRPART);
+        c->d_part = wptr<double>(c, W_SPART);
+        c->d_cchunk_ptr = wptr<int32_t>(c, W_CCHUNK);
         c->d_sys_n = wptr<int32_t>(c, W_SYSN);
         c->d_sys_nt = wptr<int32_t>(c, W_SYSNT);
         c->d_sys_toff = wptr<int64_t>(c, W_SYSTOFF);
+        c->d_sys_dof0 = wptr<int64_t>(c, W_SYSDOF0);
+        c->d_sys_cbase = wptr<int64_t>(c, W_SYSCB);
+        c->d_rt_k = wptr<int32_t>(c, W_RTK);
+        c->d_rt_nt = wptr<int32_t>(c, W_RTNT);
+        c->d_rt_cbase = wptr<int64_t>(c, W_RTCB);
+        c->d_colpart = wptr<double>(c, W_COLP);
         c->d_tiles_local = wptr<void>(c, W_TLOC);
         c->d_tiles_coarse = wptr<void>(c, W_TCOA);
         c->d_P = pc.q > 0 ? wptr<double>(c, W_P) : nullptr;
@@ -752,15 +895,10 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         c->v_I = wptr<double>(c, W_I);
         c->v_t = wptr<double>(c, W_T);
         c->v_b = wptr<double>(c, W_B);
-        c->v_r0 = wptr<double>(c, W_R0);
+        c->d_r0part = wptr<double>(c, W_R0P);
         c->v_z0 = wptr<double>(c, W_Z0);
         c->sc = wptr<DevScalars>(c, W_SC);
         c->sc_apply = wptr<DevScalars>(c, W_SCA);
-        const size_t per = c->lay.items[W_PART].bytes / 4;
-        for (int k = 0; k < 4; ++k) {
-            c->red[k].partials = reinterpret_cast<double *>(c->ws + c->lay.items[W_PART].off + k * per);
-            c->red[k].counter = reinterpret_cast<uint32_t *>(c->ws + c->lay.items[W_CNT].off + k * 64);
-        }
         c->state = S_BOUND;
     });
 }
@@ -775,6 +913,11 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             c->chunk = (int)value;
             break;
         case PDG_OPT_KERNEL_TIMING: c->timing = value != 0; break;
+        case PDG_OPT_SCHWARZ_ITEM_KB:
+            if (value < 32 || value > 8192) throw Error(PDG_EINVAL, "item size must be in 32..8192 KiB");
+            if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "set the item size before pdg_setup_preconditioner");
+            c->item_kb = (int)value;
+            break;
         default: throw Error(PDG_EINVAL, "unknown option");
         }
     });
@@ -821,8 +964,8 @@ pdg_status pdg_precond_apply(pdg_ctx *c, const double *r, double *z) {
         // restriction only (init mode: x and r untouched)
         HIPCHK(launch_update(update_args(c, 1, 0, c->v_t, const_cast<double *>(r), sc), c->stream));
         c->ev_used = 0;
-        launch_schwarz_timed(c, schwarz_args(c, 0, r, c->v_z, sc));
-        HIPCHK(launch_pupdate(pupdate_args(c, 0, z, sc), c->stream));
+        launch_schwarz_timed(c, schwarz_args(c, 0, r, sc));
+        HIPCHK(launch_pupdate(pupdate_args(c, 0, 0, z, sc), c->stream));
         if (c->timing) {
             HIPCHK(hipStreamSynchronize(c->stream));
             harvest_timing(c, 1);

@@ -2,17 +2,21 @@
 //
 // Per PCG iteration (Section 4: PCG with the additive Schwarz operator of
 // eq. (5)) the stream runs four kernels:
-//   k_spmv   (mode PQ)  q = K p, (p, q)              -> alpha = (r, z) / (p, q)
-//   k_update            x += alpha p, r -= alpha q, ||r||^2, r0 = P^T r
-//   k_schwarz           z = K_i^{-1} r_i (all subdomains), z0 = K_0^{-1} r0,
-//                       (r, z) + (r0, z0)              -> beta
-//   k_pupdate           p = z + P z0 + beta p
-// Global sums use a deterministic two-stage reduction: each workgroup writes a
-// partial sum, the last workgroup to finish (integer ticket) adds the partials
-// in a fixed order and writes the scalar.  No floating-point atomics, so two
-// runs on the same input give bitwise-equal results.  Every kernel returns at
-// once when the device-side "done" flag is set, so surplus iterations queued
-// past convergence cost a launch each and change nothing.
+//   k_spmv   (mode PQ)  q = K p, per-workgroup partials of (p, q)
+//   k_update            alpha = (r, z) / (p, q); x += alpha p, r -= alpha q;
+//                       per-chunk ||r||^2 and coarse restriction shares of P^T r
+//   k_schwarz           partial products of z_i = K_i^{-1} r_i (all subdomains)
+//                       and z0 = K_0^{-1} r0, with their shares of (r, z)
+//   k_pupdate           z = B r assembled, beta = (r, z)' / (r, z), p = z + beta p,
+//                       convergence test on ||r||^2
+// No kernel synchronises workgroups with atomics or device-scope fences (on
+// gfx950 a device-scope release fence writes back the L2 and costs tens of ns
+// per workgroup).  Instead every kernel writes per-workgroup partial sums and
+// the next kernel, after the kernel boundary, adds them in a fixed order in
+// each of its workgroups.  All sums therefore have a fixed order and two runs
+// give bitwise-equal results.  Every kernel returns at once when the
+// device-side "done" flag is set, so iterations queued past convergence cost
+// a launch each and change nothing.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -33,7 +37,7 @@ __device__ inline void wave_sum(double (&v)[NV]) {
         for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
 }
 
-// Block totals of v (valid in thread 0 only).
+// Block totals of v, returned in every thread.
 template <int NV, int BS>
 __device__ inline void block_sum(double (&v)[NV], double (&tot)[NV]) {
     __shared__ double sh[BS / 64][NV];
@@ -43,67 +47,48 @@ __device__ inline void block_sum(double (&v)[NV], double (&tot)[NV]) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) sh[w][k] = v[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int ww = 0; ww < BS / 64; ++ww) s += sh[ww][k];
-            tot[k] = s;
-        }
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int ww = 0; ww < BS / 64; ++ww) s += sh[ww][k];
+        tot[k] = s;
     }
     __syncthreads();
 }
 
-// Writes this block's partial (thread 0's `part`) and returns true in every
-// thread of the last block to arrive, with the grid totals in `tot` (thread 0).
-template <int NV, int BS>
-__device__ inline bool grid_sum(const double (&part)[NV], RedSlot red, double (&tot)[NV]) {
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red.partials[(int64_t)blockIdx.x * NV + k] = part[k];
-        __threadfence();
-        const unsigned t = atomicAdd(red.counter, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BS)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) acc[k] += __builtin_nontemporal_load(&red.partials[(int64_t)b * NV + k]);
-    block_sum<NV, BS>(acc, tot);
-    if (threadIdx.x == 0) *red.counter = 0u;
-    return true;
+// Sum of part[k * stride + slot], k < n, in a fixed order, in every thread.
+template <int BS>
+__device__ inline double block_sum_partials(const double *part, int n, int stride, int slot) {
+    double v[1] = {0.0}, t[1];
+    for (int k = threadIdx.x; k < n; k += BS) v[0] += part[(int64_t)k * stride + slot];
+    block_sum<1, BS>(v, t);
+    return t[0];
 }
 
 __device__ inline bool finite(double x) { return __builtin_isfinite(x); }
 
 // ---------------------------------------------------------------------------
 // Block-sparse SpMV over element rows in interleaved group-ELL form.
-// G = 64 / ND element rows form a group handled by one wavefront; lane
-// (r, i) = (lane / ND, lane % ND) owns output row i of the group's r-th
-// element.  Group values are stored slot-major so that for every (slot s,
-// trial index j) the wavefront reads G*ND consecutive doubles:
-//   val[((s * ND + j) * G + r) * ND + i] = K_{row_r, col_{s,r}}[i][j].
-template <int ND, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_spmv(DevMatrix A, SpmvArgs a) {
+// G = 64 / ND element rows form a group; lane (r, i) = (lane / ND, lane % ND)
+// owns output row i of the group's r-th element.  Group values are stored
+// slot-major so that for every (slot s, trial index j) a wavefront reads G*ND
+// consecutive doubles:  val[((s * ND + j) * G + r) * ND + i] = K_{row_r, col_{s,r}}[i][j].
+// One workgroup per group: its WPG wavefronts take the slots round-robin and
+// their partial sums are added in wave order through LDS.
+template <int ND, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
     if (a.mode == SPMV_PQ && a.sc->done) return;
+    __shared__ double s_acc[WPG][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t g = (int64_t)blockIdx.x * WPB + w;
+    const int64_t g = blockIdx.x;
     const int r = lane / ND, i = lane - (lane / ND) * ND;
     double acc = 0.0;
-    int row = -1;
-    if (g < A.n_groups && r < G) {
-        row = A.grp_rows[g * G + r];
+    if (r < G) {
         const int64_t s0 = A.grp_slot_off[g], ns = A.grp_slot_off[g + 1] - s0;
         const int32_t *colp = A.grp_col + s0 * G + r;
         const double *vp = A.grp_val + s0 * G * ND * ND + lane;
-        for (int64_t s = 0; s < ns; ++s) {
+        for (int64_t s = w; s < ns; s += WPG) {
             const double *xb = a.x + (int64_t)colp[s * G] * ND;
             const double *vs = vp + s * G * ND * ND;
             double v[ND];
@@ -113,7 +98,18 @@ __global__ __launch_bounds__(64 * WPB) void k_spmv(DevMatrix A, SpmvArgs a) {
             for (int j = 0; j < ND; ++j) acc = fma(v[j], xb[j], acc);
         }
     }
+    if (WPG > 1) {
+        s_acc[w][lane] = acc;
+        __syncthreads();
+        if (w == 0) {
+            acc = s_acc[0][lane];
+#pragma unroll
+            for (int k = 1; k < WPG; ++k) acc += s_acc[k][lane];
+        }
+    }
+    if (w != 0) return;  // wave 0 finishes the group
     double part[2] = {0.0, 0.0};
+    const int row = (r < G) ? A.grp_rows[g * G + r] : -1;
     if (row >= 0) {
         const int64_t idx = (int64_t)row * ND + i;
         switch (a.mode) {
@@ -152,44 +148,45 @@ __global__ __launch_bounds__(64 * WPB) void k_spmv(DevMatrix A, SpmvArgs a) {
         }
     }
     if (a.mode == SPMV_PLAIN || a.mode == SPMV_RHS) return;
-    double tot[2];
-    block_sum<2, 64 * WPB>(part, tot);
-    if (grid_sum<2, 64 * WPB>(tot, a.red, tot) && threadIdx.x == 0) {
-        DevScalars *sc = a.sc;
-        if (a.mode == SPMV_PQ) {
-            const double pq = tot[0];
+    wave_sum<2>(part);
+    if (lane == 0) {
+        a.part[2 * g] = part[0];
+        a.part[2 * g + 1] = part[1];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// alpha = (r, z) / (p, q); x += alpha p, r -= alpha q; per-chunk ||r||^2 and
+// coarse restriction shares of P^T r.  One workgroup per update chunk (a run
+// of elements inside one coarse element); the Schwarz kernel adds the shares
+// of a coarse element in chunk order when it gathers r0.
+template <int ND, int NQ>
+__global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
+    DevScalars *sc = a.sc;
+    if (sc->done) return;
+    double alpha = 0.0;
+    if (!a.init) {
+        const double pq = block_sum_partials<128>(a.pqpart, a.n_pq, 2, 0);
+        alpha = sc->rz[(a.iter - 1) & 1] / pq;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->pq = pq;
+            sc->alpha = alpha;
             if (!finite(pq)) {
                 sc->status = ST_NONFINITE;
                 sc->done = 1;
             } else if (!(pq > 0.0)) {
                 sc->status = ST_BREAKDOWN;
                 sc->done = 1;
-            } else {
-                sc->alpha = sc->rz / pq;
             }
-        } else {
-            if (a.bb_out) *a.bb_out = tot[0];
-            if (a.rr_out) *a.rr_out = tot[1];
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// x += alpha p, r -= alpha q, ||r||^2 and the coarse restriction r0 = P^T r.
-// One workgroup per update group (a coarse element, or a chunk of elements
-// when there is no coarse level) so that r0[c] is a block-local sum.
-template <int ND, int NQ>
-__global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
-    DevScalars *sc = a.sc;
-    if (sc->done) return;
-    const double alpha = a.init ? 0.0 : sc->alpha;
     const int c = blockIdx.x;
     const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * ND;
-    double v[1 + (NQ > 0 ? NQ : 1)];
+    constexpr int NV = 1 + (NQ > 0 ? NQ : 1);
+    double v[NV];
 #pragma unroll
-    for (int k = 0; k < 1 + (NQ > 0 ? NQ : 1); ++k) v[k] = 0.0;
-    for (int d = threadIdx.x; d < ndof; d += 256) {
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int d = threadIdx.x; d < ndof; d += 128) {
         const int le = d / ND, i = d - le * ND;
         const int64_t idx = (int64_t)a.grp_elems[e0 + le] * ND + i;
         double rv = a.r[idx];
@@ -205,259 +202,347 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
             for (int j = 0; j < NQ; ++j) v[1 + j] = fma(Pr[j], rv, v[1 + j]);
         }
     }
-    constexpr int NV = 1 + (NQ > 0 ? NQ : 1);
     double tot[NV];
-    block_sum<NV, 256>(v, tot);
-    if (NQ > 0 && threadIdx.x == 0)
+    block_sum<NV, 128>(v, tot);
+    if (threadIdx.x == 0) {
+        a.rrpart[c] = tot[0];
+        if (NQ > 0)
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) a.r0[c * NQ + j] = tot[1 + j];
-    double part[1] = {tot[0]}, rr[1];
-    if (grid_sum<1, 256>(part, a.red, rr) && threadIdx.x == 0) {
-        const double r2 = rr[0];
-        sc->rr = r2;
-        if (a.init) {
-            sc->iters = 0;
-            if (sc->bb == 0.0) {
-                sc->status = ST_ZERO_RHS;
-                sc->done = 1;
-            } else if (!finite(r2) || !finite(sc->bb)) {
-                sc->status = ST_NONFINITE;
-                sc->done = 1;
-            } else if (r2 <= sc->tol2 * sc->bb) {
-                sc->status = ST_CONV;
-                sc->done = 1;
-            }
-        } else {
-            sc->iters = a.iter;
-            if (!finite(r2)) {
-                sc->status = ST_NONFINITE;
-                sc->done = 1;
-            } else if (r2 <= sc->tol2 * sc->bb) {
-                sc->status = ST_CONV;
-                sc->done = 1;
-            } else if (a.iter >= sc->maxit) {
-                sc->status = ST_NOCONV;
-                sc->done = 1;
-            }
-        }
+            for (int j = 0; j < NQ; ++j) a.r0part[c * NQ + j] = tot[1 + j];
     }
 }
 
 // ---------------------------------------------------------------------------
 // Schwarz apply: z_i = K_i^{-1} r_i for every subdomain and z0 = K_0^{-1} r0.
 // Each inverse is symmetric and stored as packed lower-triangular 64x64 tiles
-// (row-major inside a tile).  A workgroup (256 threads) owns one 64-row tile
-// row I of one system and streams the nt tiles of that row: tile (I, J) for
-// J <= I used as stored, tile (J, I) for J > I used transposed.  Each thread
-// loads 16 bytes per tile row for RPT rows, so every load instruction of a
-// wavefront reads whole contiguous tile rows.
+// (row-major inside a tile).  A workgroup (256 threads) owns one work item:
+// tile columns [j0, j0 + nj) of one 64-row tile row I of one system, using
+// tile (I, J) as stored for J <= I and tile (J, I) transposed for J > I.  Each
+// thread loads 16 bytes per tile row for RPT rows, so every load instruction
+// of a wavefront reads whole contiguous tile rows; the next tile is loaded
+// while the current one is multiplied.  Items hold ~256 KB of tiles, so the
+// grid is many similar-sized workgroups.
 template <typename E> struct AccT { using T = float; };
 template <> struct AccT<double> { using T = double; };
 
-struct alignas(16) Vec16 { uint32_t w[4]; };
+// 16-byte load type per storage type; element c of a loaded vector as the
+// accumulation type.
+template <typename E> struct Ld;
+template <> struct Ld<double> {
+    using V = double2;
+    static __device__ inline double get(const V &v, int c) { return c == 0 ? v.x : v.y; }
+};
+template <> struct Ld<float> {
+    using V = float4;
+    static __device__ inline float get(const V &v, int c) {
+        return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+    }
+};
+template <> struct Ld<uint16_t> {
+    using V = uint4;
+    static __device__ inline float get(const V &v, int c) {
+        const uint32_t w = (c >> 1) == 0 ? v.x : ((c >> 1) == 1 ? v.y : ((c >> 1) == 2 ? v.z : v.w));
+        return __uint_as_float((c & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+};
 
-template <typename E, int CW>
-__device__ inline void unpack(const Vec16 &v, typename AccT<E>::T (&out)[CW]);
-
-template <>
-__device__ inline void unpack<double, 2>(const Vec16 &v, double (&out)[2]) {
-    out[0] = __hiloint2double(v.w[1], v.w[0]);
-    out[1] = __hiloint2double(v.w[3], v.w[2]);
-}
-template <>
-__device__ inline void unpack<float, 4>(const Vec16 &v, float (&out)[4]) {
+// Multiply-accumulate of one 64x64 tile held in registers (RPT rows of CW
+// columns per thread): tile (I, J) as stored (J <= I) or transposed (J > I).
+template <typename E, int CW, int RPT>
+__device__ inline void tile_mac(const typename Ld<E>::V (&tv)[RPT], bool stored, const typename AccT<E>::T *xJ,
+                                int cg, int rg, typename AccT<E>::T (&accR)[RPT],
+                                typename AccT<E>::T (&accC)[CW]) {
+    using A = typename AccT<E>::T;
+    if (stored) {
+        A xb[CW];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = __uint_as_float(v.w[k]);
-}
-template <>
-__device__ inline void unpack<uint16_t, 8>(const Vec16 &v, float (&out)[8]) {
+        for (int c = 0; c < CW; ++c) xb[c] = xJ[cg * CW + c];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        out[2 * k] = __uint_as_float(v.w[k] << 16);
-        out[2 * k + 1] = __uint_as_float(v.w[k] & 0xffff0000u);
+        for (int k = 0; k < RPT; ++k)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) accR[k] = fma((A)Ld<E>::get(tv[k], c), xb[c], accR[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const A xa = xJ[rg * RPT + k];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) accC[c] = fma((A)Ld<E>::get(tv[k], c), xa, accC[c]);
+        }
     }
 }
 
+// Coarse residual entry gi = (coarse element, basis index): the sum of the
+// restriction shares of the coarse element's update chunks, in chunk order.
+__device__ inline double coarse_r0(const SchwarzArgs &a, int gi) {
+    const int nq = a.nq0;
+    const int cc = gi / nq, j = gi - cc * nq;
+    double v = 0.0;
+    for (int ch = a.cchunk_ptr[cc]; ch < a.cchunk_ptr[cc + 1]; ++ch) v += a.r0part[ch * nq + j];
+    return v;
+}
+
+// Entry gi of the input vector of system s (local: r on the subdomain's dofs;
+// coarse: r0).
+__device__ inline double sys_input(const SchwarzArgs &a, int s, bool coarse, int64_t dof0, int gi) {
+    if (coarse) return coarse_r0(a, gi);
+    if (dof0 >= 0) return a.r[dof0 + gi];
+    const int nd = a.nd;
+    const int le = gi / nd, i = gi - le * nd;
+    return a.r[(int64_t)a.sub_elems[a.sub_ptr[s] + le] * nd + i];
+}
+
+// One work item: stored tiles (I, J), J in [j0, j0 + nj), of packed tile row
+// I of system s (J <= I).  Each tile is read once and used twice:
+//   row use      y_I += T x_J   (accumulated in registers over the item)
+//   column use   y_J  = T^T x_I (J < I; reduced across the row groups with
+//                wave shuffles and one double-buffered LDS exchange, written as
+//                the tile's column partial)
+// The first two tiles are requested before x is gathered into LDS so their
+// latency overlaps the gather.  Tiles then stream through two register
+// buffers A and B in a fixed ping-pong (no register copies, no conditional
+// loads in the steady state).  Barriers only wait for LDS traffic, so tile
+// loads stay in flight across them.  Outputs: the item's row partial in yout,
+// the FP64 input entry of row I in *r_own (threads < 64), and in *dot_col the
+// thread's share of sum_J (x_J, column partial of J).
 template <typename E>
-__device__ inline void tile_row_product(const E *__restrict__ tiles, int64_t toff, int nt, int I,
-                                        const typename AccT<E>::T *xs, typename AccT<E>::T *yout,
-                                        typename AccT<E>::T *scratch) {
+__device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ tiles, int s, int I, int j0,
+                                    int nj, bool coarse, double *smem, int max_nj, double *yout,
+                                    double *r_own, double *dot_col) {
     using A = typename AccT<E>::T;
+    using V = typename Ld<E>::V;
     constexpr int CW = 16 / sizeof(E);  // columns per 16-byte load
     constexpr int NC = TILE / CW;       // column groups per tile row
     constexpr int RG = 256 / NC;        // row groups
     constexpr int RPT = TILE / RG;      // rows per thread
-    const int tid = threadIdx.x, cg = tid % NC, rg = tid / NC;
-    A accR[RPT], accC[CW];
+    const int tid = threadIdx.x, cg = tid % NC, rg = tid / NC, lane = tid & 63, wv = tid >> 6;
+    const int n = a.sys_n[s];
+    const int64_t toff = a.sys_toff[s];
+    const int64_t cbase = a.sys_cbase[s] + (int64_t)I * (I + 1) / 2;
+    const int64_t dof0 = coarse ? -1 : a.sys_dof0[s];
+    // LDS: x in FP64 (columns, then row I), x in the accumulation type, column exchange
+    double *x64 = smem;
+    double *xI64 = x64 + max_nj * TILE;
+    A *xa = sizeof(A) == 8 ? reinterpret_cast<A *>(x64) : reinterpret_cast<A *>(xI64 + TILE);
+    A *xIa = xa + max_nj * TILE;
+    A *colx = reinterpret_cast<A *>(smem) + (sizeof(A) == 8 ? 1 : 3) * (max_nj + 1) * TILE;  // [2][4][64]
+    auto tile_ptr = [&](int J) -> const E * {
+        return tiles + (toff + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE) + (rg * RPT) * TILE + cg * CW;
+    };
+    auto load = [&](V (&buf)[RPT], int J) {
+        const E *tp = tile_ptr(J);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) buf[k] = *reinterpret_cast<const V *>(tp + k * TILE);
+    };
+    A accR[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) accR[k] = 0;
+    V bA[RPT], bB[RPT];
+    const int npair = nj >> 1;
+    if (npair > 0) {
+        load(bA, j0);
+        load(bB, j0 + 1);
+    }
+    // gather x over the item's tile columns and over tile row I
+    const int base = j0 * TILE;
+    for (int t = tid; t < nj * TILE; t += 256) {
+        const int gi = base + t;
+        const double v = gi < n ? sys_input(a, s, coarse, dof0, gi) : 0.0;
+        x64[t] = v;
+        if (sizeof(A) != 8) xa[t] = (A)v;
+    }
+    if (tid < TILE) {
+        const int gi = I * TILE + tid;
+        const double v = gi < n ? sys_input(a, s, coarse, dof0, gi) : 0.0;
+        xI64[tid] = v;
+        if (sizeof(A) != 8) xIa[tid] = (A)v;
+        *r_own = v;
+    }
+    __syncthreads();
+    double dcol = 0.0;
+    int par = 0;
+    // one tile: row use always, column use below the diagonal
+    auto tile_step = [&](const V (&buf)[RPT], int jj) {
+        const int J = j0 + jj;
+        const A *xJ = (sizeof(A) == 8 ? reinterpret_cast<const A *>(x64) : xa) + jj * TILE;
+        const A *xIv = sizeof(A) == 8 ? reinterpret_cast<const A *>(xI64) : xIa;
+        A xb[CW], cacc[CW];
 #pragma unroll
-    for (int c = 0; c < CW; ++c) accC[c] = 0;
-    auto tile_ptr = [&](int J) -> const E * {
-        const int64_t t = (J <= I) ? ((int64_t)I * (I + 1) / 2 + J) : ((int64_t)J * (J + 1) / 2 + I);
-        return tiles + (toff + t) * (TILE * TILE) + (rg * RPT) * TILE + cg * CW;
+        for (int c = 0; c < CW; ++c) {
+            xb[c] = xJ[cg * CW + c];
+            cacc[c] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const A xr = xIv[rg * RPT + k];
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const A t = (A)Ld<E>::get(buf[k], c);
+                accR[k] = fma(t, xb[c], accR[k]);
+                cacc[c] = fma(t, xr, cacc[c]);
+            }
+        }
+        if (J < I) {
+            // sum over the row groups inside the wavefront, then over the 4 wavefronts
+#pragma unroll
+            for (int off = NC; off < 64; off <<= 1)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) cacc[c] += __shfl_xor(cacc[c], off, 64);
+            A *cx = colx + par * 4 * TILE;
+            if (lane < NC)
+#pragma unroll
+                for (int c = 0; c < CW; ++c) cx[wv * TILE + cg * CW + c] = cacc[c];
+            __syncthreads();
+            if (tid < TILE) {
+                const double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
+                                 (double)cx[3 * TILE + tid];
+                a.colpart[(cbase + J) * TILE + tid] = v;
+                dcol = fma(x64[jj * TILE + tid], v, dcol);
+            }
+            par ^= 1;
+        }
     };
-    Vec16 cur[RPT], nxt[RPT];
-    {
-        const E *tp = tile_ptr(0);
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) cur[k] = *reinterpret_cast<const Vec16 *>(tp + k * TILE);
-    }
-    for (int J = 0; J < nt; ++J) {
-        if (J + 1 < nt) {
-            const E *tp = tile_ptr(J + 1);
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) nxt[k] = *reinterpret_cast<const Vec16 *>(tp + k * TILE);
+    int jj = 0;
+    if (npair > 0) {
+        for (; jj + 2 < 2 * npair; jj += 2) {
+            const int J = j0 + jj;
+            // scheduling barriers keep each refill after the multiply that frees its buffer
+            tile_step(bA, jj);
+            __builtin_amdgcn_sched_barrier(0);
+            load(bA, J + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            tile_step(bB, jj + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            load(bB, J + 3);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        const A *xJ = xs + J * TILE;
-        if (J <= I) {
-            A xb[CW];
-#pragma unroll
-            for (int c = 0; c < CW; ++c) xb[c] = xJ[cg * CW + c];
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                A t[CW];
-                unpack<E, CW>(cur[k], t);
-#pragma unroll
-                for (int c = 0; c < CW; ++c) accR[k] = fma(t[c], xb[c], accR[k]);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const A xa = xJ[rg * RPT + k];
-                A t[CW];
-                unpack<E, CW>(cur[k], t);
-#pragma unroll
-                for (int c = 0; c < CW; ++c) accC[c] = fma(t[c], xa, accC[c]);
-            }
-        }
-        if (J + 1 < nt)
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) cur[k] = nxt[k];
+        tile_step(bA, jj);
+        tile_step(bB, jj + 1);
+        jj += 2;
     }
-    __syncthreads();  // scratch aliases xs
-    A *sR = scratch, *sC = scratch + 256 * RPT;
+    if (jj < nj) {  // odd count: last tile on its own
+        load(bA, j0 + jj);
+        tile_step(bA, jj);
+    }
+    *dot_col = dcol;
+    __syncthreads();  // the reduction scratch aliases the x buffers
+    A *sR = reinterpret_cast<A *>(smem);
 #pragma unroll
     for (int k = 0; k < RPT; ++k) sR[(rg * NC + cg) * RPT + k] = accR[k];
-#pragma unroll
-    for (int c = 0; c < CW; ++c) sC[(rg * NC + cg) * CW + c] = accC[c];
     __syncthreads();
     if (tid < TILE) {
-        const int a = tid;
+        const int ar = tid;
         A y = 0;
-        const int arg = a / RPT, ak = a % RPT;
+        const int arg = ar / RPT, ak = ar % RPT;
         for (int c = 0; c < NC; ++c) y += sR[(arg * NC + c) * RPT + ak];
-        const int acg = a / CW, ac = a % CW;
-        for (int g = 0; g < RG; ++g) y += sC[(g * NC + acg) * CW + ac];
-        yout[a] = y;
+        yout[ar] = (double)y;
     }
     __syncthreads();
-}
-
-template <typename E>
-__device__ inline void schwarz_item(const SchwarzArgs &a, const E *tiles, int s, int I, bool coarse,
-                                    double *smem, double &y_out, int &out_idx_valid, int64_t &out_idx) {
-    using A = typename AccT<E>::T;
-    const int n = a.sys_n[s], nt = a.sys_nt[s];
-    const int64_t toff = a.sys_toff[s];
-    A *xs = reinterpret_cast<A *>(smem);
-    __shared__ double yout_d[TILE];
-    A *yout = reinterpret_cast<A *>(yout_d);
-    const int nd = a.nd;
-    int e0 = 0;
-    if (!coarse) {
-        e0 = a.sub_ptr[s];
-        for (int t = threadIdx.x; t < nt * TILE; t += 256) {
-            A v = 0;
-            if (t < n) {
-                const int le = t / nd, i = t - le * nd;
-                v = (A)a.r[(int64_t)a.sub_elems[e0 + le] * nd + i];
-            }
-            xs[t] = v;
-        }
-    } else {
-        for (int t = threadIdx.x; t < nt * TILE; t += 256) xs[t] = t < n ? (A)a.r0[t] : (A)0;
-    }
-    __syncthreads();
-    tile_row_product<E>(tiles, toff, nt, I, xs, yout, xs);
-    out_idx_valid = 0;
-    if (threadIdx.x < TILE) {
-        const int gi = I * TILE + threadIdx.x;
-        if (gi < n) {
-            y_out = (double)yout[threadIdx.x];
-            out_idx_valid = 1;
-            if (!coarse) {
-                const int le = gi / nd, i = gi - le * nd;
-                out_idx = (int64_t)a.sub_elems[e0 + le] * nd + i;
-            } else {
-                out_idx = gi;
-            }
-        }
-    }
 }
 
 template <typename EL, typename EC>
-__global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a) {
+__global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a, int max_nj) {
     if (a.mode != 0 && a.sc->done) return;
     extern __shared__ double smem[];
-    const int item = blockIdx.x;
-    const int s = a.item_sys[item], I = a.item_row[item];
+    __shared__ double yout[TILE];
+    const int item = blockIdx.x, tid = threadIdx.x;
+    const int s = a.item_sys[item], I = a.item_row[item], j0 = a.item_j0[item], nj = a.item_nj[item];
     const bool coarse = s >= a.n_sub;
-    double y = 0.0;
-    int valid = 0;
-    int64_t idx = 0;
+    double r_own = 0.0, dcol = 0.0;
     if (!coarse)
-        schwarz_item<EL>(a, reinterpret_cast<const EL *>(a.tiles_local), s, I, false, smem, y, valid, idx);
+        schwarz_item<EL>(a, reinterpret_cast<const EL *>(a.tiles_local), s, I, j0, nj, false, smem, max_nj, yout,
+                         &r_own, &dcol);
     else
-        schwarz_item<EC>(a, reinterpret_cast<const EC *>(a.tiles_coarse), s, I, true, smem, y, valid, idx);
-    double part[1] = {0.0};
-    if (valid) {
-        if (!coarse) {
-            a.z[idx] = y;
-            part[0] = a.r[idx] * y;
-        } else {
-            a.z0[idx] = y;
-            part[0] = a.r0[idx] * y;
-        }
-    }
-    if (a.mode == 0) return;
-    double tot[1];
-    block_sum<1, 256>(part, tot);
-    if (grid_sum<1, 256>(tot, a.red, tot) && threadIdx.x == 0) {
-        DevScalars *sc = a.sc;
-        const double rz = tot[0];
-        if (!finite(rz)) {
-            sc->status = ST_NONFINITE;
-            sc->done = 1;
-        } else if (!(rz > 0.0)) {
-            sc->status = ST_BREAKDOWN;
-            sc->done = 1;
-        } else {
-            sc->beta = (a.mode == 1) ? 0.0 : rz / sc->rz;
-            sc->rz = rz;
+        schwarz_item<EC>(a, reinterpret_cast<const EC *>(a.tiles_coarse), s, I, j0, nj, true, smem, max_nj, yout,
+                         &r_own, &dcol);
+    if (tid < TILE) {
+        const double y = yout[tid];
+        a.part[(int64_t)item * TILE + tid] = y;
+        if (a.mode != 0) {
+            // this item's share of (r, z): row I times the row partial, plus the
+            // column partials times their x_J
+            double v[1] = {fma(r_own, y, dcol)};
+            wave_sum<1>(v);
+            if (tid == 0) a.itemdot[item] = v[0];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// p = z + P z0 (+ beta p): prolongation of the coarse correction fused with
-// the search-direction update.
+// z = B r assembled from the Schwarz items (tile rows of the local solves plus
+// the prolongation P z0 of the coarse solve), and the search direction
+// p = z (+ beta p).  In PCG modes every workgroup first forms (r, z) from the
+// items' shares (fixed order) to get beta; workgroup 0 also closes the
+// iteration: ||r||^2 from the update chunks, convergence / breakdown flags.
+__device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) {
+    double v = 0.0;
+    for (int it = a.rt_item0[rt]; it < a.rt_item0[rt + 1]; ++it) v += a.part[(int64_t)it * TILE + lane];
+    // column partials of the stored tiles (I, K), I > K, below this tile row
+    const int K = a.rt_k[rt], nt = a.rt_nt[rt];
+    const int64_t cb = a.rt_cbase[rt];
+    for (int I = K + 1; I < nt; ++I) v += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
+    return v;
+}
+
 template <int NQ>
 __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
-    if (a.mode != 0 && a.sc->done) return;
+    DevScalars *sc = a.sc;
+    if (a.mode != 0 && sc->done) return;
+    double beta = 0.0;
+    if (a.mode != 0) {
+        const double rz = block_sum_partials<256>(a.itemdot, a.n_items, 1, 0);
+        if (a.mode == 2) beta = rz / sc->rz[(a.iter - 1) & 1];
+        if (blockIdx.x == 0) {
+            const double rr = block_sum_partials<256>(a.rrpart, a.n_rr, 1, 0);
+            double bb = 0.0;
+            if (a.mode == 1) bb = block_sum_partials<256>(a.bbpart, a.n_bb, 2, 0);
+            if (threadIdx.x == 0) {
+                if (a.mode == 1) sc->bb = bb;
+                bb = sc->bb;
+                sc->rr = rr;
+                sc->rz[a.iter & 1] = rz;
+                sc->beta = beta;
+                sc->iters = a.iter;
+                if (a.mode == 1 && bb == 0.0) {
+                    sc->status = ST_ZERO_RHS;
+                    sc->done = 1;
+                } else if (!finite(rr) || !finite(bb) || !finite(rz)) {
+                    sc->status = ST_NONFINITE;
+                    sc->done = 1;
+                } else if (rr <= sc->tol2 * bb) {
+                    sc->status = ST_CONV;
+                    sc->done = 1;
+                } else if (!(rz > 0.0)) {
+                    sc->status = ST_BREAKDOWN;
+                    sc->done = 1;
+                } else if (a.iter >= sc->maxit) {
+                    sc->status = ST_NOCONV;
+                    sc->done = 1;
+                }
+            }
+        }
+    }
     const int64_t n = a.n_elem * a.nd;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= n) return;
-    double zz = a.z[idx];
+    const int dr = a.dof_rt[idx];
+    double zz = tile_row_value(a, dr >> 6, dr & 63);
     if (NQ > 0) {
         const int64_t e = idx / a.nd;
-        const double *z0 = a.z0 + (int64_t)a.elem_coarse[e] * NQ;
+        const int c0 = a.elem_coarse[e] * NQ;
         const double *Pr = a.P + idx * NQ;
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], z0[j], zz);
+        for (int j = 0; j < NQ; ++j) {
+            const int gi = c0 + j;
+            zz = fma(Pr[j], tile_row_value(a, a.coarse_rt0 + (gi >> 6), gi & 63), zz);
+        }
     }
-    if (a.mode == 2) zz = fma(a.sc->beta, a.p[idx], zz);
+    if (a.mode == 2) zz = fma(beta, a.p[idx], zz);
     a.p[idx] = zz;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double *part, int n, int slot, double *out) {
+    const double t = block_sum_partials<256>(part, n, 2, slot);
+    if (threadIdx.x == 0) *out = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -701,7 +786,8 @@ __global__ void k_zero(double *x, int64_t n) {
 __global__ void k_status_reset(DevScalars *sc, double tol2, int maxit, int reset_ionic) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         if (reset_ionic) sc->ionic_bad = 0;
-        sc->bb = sc->rr = sc->rz = sc->pq = sc->alpha = sc->beta = sc->tr = 0.0;
+        sc->bb = sc->rr = sc->pq = sc->alpha = sc->beta = sc->tr = 0.0;
+        sc->rz[0] = sc->rz[1] = 0.0;
         sc->tol2 = tol2;
         sc->done = 0;
         sc->status = ST_RUN;
@@ -712,13 +798,13 @@ __global__ void k_status_reset(DevScalars *sc, double tol2, int maxit, int reset
 
 // ---------------------------------------------------------------------------
 // launchers
-constexpr int kSpmvWPB = 2;
+constexpr int kSpmvWPG = 4;
 
-int spmv_blocks(const DevMatrix &A) { return (int)((A.n_groups + kSpmvWPB - 1) / kSpmvWPB); }
+int spmv_blocks(const DevMatrix &A) { return (int)A.n_groups; }
 
 template <int ND>
 static hipError_t spmv_nd(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv<ND, kSpmvWPB>), dim3(spmv_blocks(A)), dim3(64 * kSpmvWPB), 0, s, A, a);
+    hipLaunchKernelGGL((k_spmv<ND, kSpmvWPG>), dim3(spmv_blocks(A)), dim3(64 * kSpmvWPG), 0, s, A, a);
     return hipGetLastError();
 }
 
@@ -738,9 +824,9 @@ hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
 template <int ND>
 static hipError_t update_nd(const UpdateArgs &a, hipStream_t s) {
     switch (a.nq0) {
-    case 0: hipLaunchKernelGGL((k_update<ND, 0>), dim3(a.n_grp), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_update<ND, 3>), dim3(a.n_grp), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_update<ND, 4>), dim3(a.n_grp), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_update<ND, 0>), dim3(a.n_grp), dim3(128), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_update<ND, 3>), dim3(a.n_grp), dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_update<ND, 4>), dim3(a.n_grp), dim3(128), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -762,33 +848,41 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t s) {
 template <typename E> static constexpr size_t acc_size() { return sizeof(typename AccT<E>::T); }
 template <typename E> static constexpr size_t scratch_bytes() {
     constexpr int CW = 16 / sizeof(E), NC = TILE / CW, RG = 256 / NC, RPT = TILE / RG;
-    return (size_t)256 * (RPT + CW) * acc_size<E>();
+    return (size_t)256 * RPT * acc_size<E>();
 }
 
 template <typename EL, typename EC>
-static hipError_t schwarz_t(const SchwarzArgs &a, int n_items, int max_n, hipStream_t s) {
-    const size_t nt_max = (size_t)(max_n + TILE - 1) / TILE;
-    size_t bytes = nt_max * TILE * (acc_size<EL>() > acc_size<EC>() ? acc_size<EL>() : acc_size<EC>());
-    const size_t sb = scratch_bytes<EL>() > scratch_bytes<EC>() ? scratch_bytes<EL>() : scratch_bytes<EC>();
-    if (bytes < sb) bytes = sb;
-    hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_items), dim3(256), bytes, s, a);
+static hipError_t schwarz_t(const SchwarzArgs &a, int n_items, int max_nj, hipStream_t s) {
+    // x (FP64, columns + row I), x in the accumulation type, column exchange [2][4][64];
+    // the final row reduction (256 * RPT values) reuses the same space
+    auto need = [&](size_t acc, size_t scratch) {
+        size_t b = (size_t)(max_nj + 1) * TILE * 8 + (acc == 8 ? 0 : (size_t)(max_nj + 1) * TILE * acc);
+        b = (b + 15) & ~(size_t)15;
+        size_t x_end = (acc == 8 ? 1 : 3) * (size_t)(max_nj + 1) * TILE * acc;  // offset of the exchange area
+        if (x_end > b) b = x_end;
+        b += 2 * 4 * TILE * acc;
+        return b > scratch ? b : scratch;
+    };
+    const size_t bl = need(acc_size<EL>(), scratch_bytes<EL>()), bc = need(acc_size<EC>(), scratch_bytes<EC>());
+    const size_t bytes = bl > bc ? bl : bc;
+    hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_items), dim3(256), bytes, s, a, max_nj);
     return hipGetLastError();
 }
 
-hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store, int max_n,
+hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store, int max_nj,
                           hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (coarse_store == STORE_F64) {
         switch (local_store) {
-        case STORE_F64: return schwarz_t<double, double>(a, n_items, max_n, s);
-        case STORE_F32: return schwarz_t<float, double>(a, n_items, max_n, s);
-        case STORE_BF16: return schwarz_t<uint16_t, double>(a, n_items, max_n, s);
+        case STORE_F64: return schwarz_t<double, double>(a, n_items, max_nj, s);
+        case STORE_F32: return schwarz_t<float, double>(a, n_items, max_nj, s);
+        case STORE_BF16: return schwarz_t<uint16_t, double>(a, n_items, max_nj, s);
         }
     } else {
         switch (local_store) {
-        case STORE_F64: return schwarz_t<double, float>(a, n_items, max_n, s);
-        case STORE_F32: return schwarz_t<float, float>(a, n_items, max_n, s);
-        case STORE_BF16: return schwarz_t<uint16_t, float>(a, n_items, max_n, s);
+        case STORE_F64: return schwarz_t<double, float>(a, n_items, max_nj, s);
+        case STORE_F32: return schwarz_t<float, float>(a, n_items, max_nj, s);
+        case STORE_BF16: return schwarz_t<uint16_t, float>(a, n_items, max_nj, s);
         }
     }
     return hipErrorInvalidValue;
@@ -802,6 +896,11 @@ hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s) {
     case 4: hipLaunchKernelGGL((k_pupdate<4>), dim3(blocks), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *part, int n, int slot, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, n, slot, out);
     return hipGetLastError();
 }
 

@@ -173,10 +173,13 @@ class Context:
         return info.as_dict()
 
 
-def from_problem(problem, device="cuda:0", local_prec=None, coarse_prec=None, bind=True):
+def from_problem(problem, device="cuda:0", local_prec=None, coarse_prec=None, bind=True, options=None):
     """Context set up for a workload object with the attributes of
-    ``pdg_inputs.problems.Problem`` (mesh, p, constants, partitions, ionic)."""
+    ``pdg_inputs.problems.Problem`` (mesh, p, constants, partitions, ionic).
+    ``options``: {pdg option id: value} applied right after creation."""
     ctx = Context(device)
+    for k, v in (options or {}).items():
+        ctx.set_option(k, v)
     ctx.set_mesh(problem.mesh, problem.p)
     ctx.assemble(problem.chi_m, problem.c_m, problem.dt, problem.eta0)
     ctx.set_ionic(problem.ionic)
