@@ -479,8 +479,17 @@ __device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) 
     // column partials of the stored tiles (I, K), I > K, below this tile row
     const int K = a.rt_k[rt], nt = a.rt_nt[rt];
     const int64_t cb = a.rt_cbase[rt];
-    for (int I = K + 1; I < nt; ++I) v += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
-    return v;
+    // four independent partial sums (fixed order) so the loads overlap
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int I = K + 1;
+    for (; I + 3 < nt; I += 4) {
+        c0 += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
+        c1 += a.colpart[(cb + (int64_t)(I + 1) * (I + 2) / 2 + K) * TILE + lane];
+        c2 += a.colpart[(cb + (int64_t)(I + 2) * (I + 3) / 2 + K) * TILE + lane];
+        c3 += a.colpart[(cb + (int64_t)(I + 3) * (I + 4) / 2 + K) * TILE + lane];
+    }
+    for (; I < nt; ++I) c0 += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
+    return v + ((c0 + c1) + (c2 + c3));
 }
 
 template <int NQ>
