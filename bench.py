@@ -7,6 +7,10 @@ x0 = U^k -- all in libpdg's HIP kernels.  Workload (default): 3-D cube [0, 10 mm
 regions (conductivity 1:3), 64 subdomains of uneven size (+-40 %) with a P1
 coarse space on them, planar stimulus, plain FP64.
 
+``--workload cfg4`` runs the batching form instead: 64 independent systems
+(~1.05M dofs, p = 1..4) in one context per degree, each on its own stream,
+stepped together (pdg_step_batch) with PCG chunks replayed as captured graphs.
+
 Prints one JSON line (see the design doc for the fields).  Inputs are resident in
 HBM before the timed region starts.
 """
@@ -79,12 +83,139 @@ def cpu_baseline(problem, n_steps=1):
     }
 
 
+def cpu_baseline_batch(batch, min_dofs=40000):
+    """The oracle on a bounded sample of the batch: the first systems (in
+    generation order) up to `min_dofs` dofs, one CN step each, setup untimed."""
+    from oracle.monodomain import Monodomain
+    cores = len(os.sched_getaffinity(0))
+    picked, tot = [], 0
+    for i, q in enumerate(batch.systems):
+        picked.append(i)
+        tot += q.n_dof
+        if tot >= min_dofs:
+            break
+    t_step, iters = 0.0, []
+    for i in picked:
+        md = Monodomain(batch.systems[i])
+        U, Up, Y = md.initial_state()
+        t0 = time.perf_counter()
+        U, Up, Y, info = md.step(U, Up, Y)
+        t_step += time.perf_counter() - t0
+        iters.append(info.iters)
+    return {
+        "value": tot / t_step / 1e6,
+        "unit": "MDoF/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"first CN step of batch systems {picked} ({tot} dofs, FP64 Schwarz, setup untimed), "
+                  f"{t_step:.1f} s, PCG iters {iters}",
+    }
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2512_19536_amd import _lib
+    from paper_2512_19536_amd.solver import BatchSolver
+    from pdg_inputs import problems
+
+    t0 = time.perf_counter()
+    batch = problems.cfg4()
+    log(f"[bench] workload cfg4: {len(batch.systems)} systems, {batch.n_dof} dofs, degrees "
+        f"{ {p: len(ix) for p, (_, ix) in batch.groups.items()} }; inputs {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    opts = {_lib.PDG_OPT_GRAPH: args.graph, _lib.PDG_OPT_CHUNK: args.chunk}
+    bs = BatchSolver(batch, device="cuda:0", options=opts)
+    torch.cuda.synchronize()
+    log(f"[bench] library setup {time.perf_counter() - t0:.1f} s")
+    tune = None
+    if args.autotune:
+        tune = [c.autotune(reps=10) for c in bs.ctxs]
+        log(f"[bench] autotune: {tune}")
+    U, Up, Y = bs.initial_state()
+    tol, maxit = 1e-10, 5000
+    for k in range(args.warmup):
+        infos = bs.step(U, Up, Y, tol, maxit)
+        log(f"[bench] warmup step {k}: iters per degree {[i['iters'] for i in infos]}")
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        infos = bs.step(U, Up, Y, tol, maxit)
+        iters.append([i["iters"] for i in infos])
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    sys_iters = [bs.system_info(i)["iters"] for i in range(len(batch.systems))]
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step; max iters per degree {iters[-1]}; "
+        f"system iters last step min {min(sys_iters)} max {max(sys_iters)}")
+    # kernel timing of the Schwarz apply: one step per context, contexts one after the other
+    launches, tot_ms, tot_bytes = 0, 0.0, 0.0
+    for ci, c in enumerate(bs.ctxs):
+        c.set_option(_lib.PDG_OPT_KERNEL_TIMING, 1)
+        c.kernel_timing()
+        c.step(U[ci], Up[ci], Y[ci], None, tol, maxit)
+        n, ms, by = c.kernel_timing()
+        c.set_option(_lib.PDG_OPT_KERNEL_TIMING, 0)
+        launches += n
+        tot_ms += ms
+        tot_bytes += n * by
+        log(f"[bench] p={bs.problems[ci].p}: schwarz apply {n} launches, avg {ms / max(n, 1) * 1e3:.1f} us, "
+            f"{by / 1e6:.1f} MB -> {by / (ms / max(n, 1) * 1e-3) / 1e9 if n else 0:.0f} GB/s")
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle ...")
+        cpu = cpu_baseline_batch(batch)
+        log(f"[bench] cpu baseline: {cpu['value']:.4f} MDoF/s")
+    out = {
+        "metric": METRIC,
+        "value": round(batch.n_dof / (ms_step * 1e-3) / 1e6, 3),
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32-schwarz",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"cfg4: batch of {len(batch.systems)} independent 3-D polytopal problems, "
+                         f"{batch.n_dof} dofs in total (2k-60k each, p=1..4), ~250-dof subdomains + P1 coarse "
+                         f"per system, Schwarz f32/f32, relres 1e-10, one context per degree on its own stream, "
+                         f"graph replay {'on' if args.graph else 'off'}"),
+            "n_dof": batch.n_dof, "n_systems": len(batch.systems),
+        },
+        "pcg_iters": {"max_per_step": int(np.max(iters)), "systems_last_step": {"min": min(sys_iters),
+                                                                                 "max": max(sys_iters)}},
+        "autotune": tune,
+        "roofline": {
+            "kernel": "k_schwarz (local + coarse inverse-tile products), all degree contexts",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes_per_launch": int(tot_bytes / max(launches, 1)),
+            "avg_launch_us": round(tot_ms / max(launches, 1) * 1e3, 2),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--graph", type=int, default=None, help="replay PCG chunks as captured graphs (0/1)")
+    ap.add_argument("--chunk", type=int, default=4, help="PCG iterations between host polls")
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--local-prec", default=None, choices=["f64", "f32", "bf16"])
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--item-kb", type=int, default=None, help="Schwarz work-item size (KiB of tiles)")
@@ -95,6 +226,13 @@ def main():
         print("bench.py: this build runs on one GPU only; a multi-GPU run is not provided "
               "(see DESIGN.md for how the path would shard).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "cfg4":
+        if args.graph is None:
+            args.graph = 1
+        return bench_batch(args)
+    if args.graph is None:
+        args.graph = 0
 
     import numpy as np
     import torch
@@ -111,16 +249,27 @@ def main():
     log(f"[bench] workload {pr.name}: {pr.n_elem} elements, p={pr.p}, {pr.n_dof} dofs, "
         f"{pr.n_sub} subdomains; inputs {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    opts = {_lib.PDG_OPT_SCHWARZ_ITEM_KB: args.item_kb} if args.item_kb else None
-    ctx = from_problem(pr, device=dev, options=opts)
+    opts = {_lib.PDG_OPT_CHUNK: args.chunk}
+    if args.item_kb:
+        opts[_lib.PDG_OPT_SCHWARZ_ITEM_KB] = args.item_kb
+    stream = None
+    if args.graph:
+        opts[_lib.PDG_OPT_GRAPH] = 1
+        stream = torch.cuda.Stream(device=dev)
+    ctx = from_problem(pr, device=dev, options=opts, stream=stream)
     torch.cuda.synchronize()
     log(f"[bench] library setup (assembly, Schwarz inverses, upload) {time.perf_counter() - t0:.1f} s")
+    if args.autotune:
+        log(f"[bench] autotune: {ctx.autotune(reps=10)}")
     U, Up, Y = initial_state(ctx, pr)
     stream = ctx.stream
     for k in range(args.warmup):
         info = ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
         log(f"[bench] warmup step {k}: iters {info['iters']}")
-    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 1)
+    # Schwarz kernel timed with HIP events inside the timed region; with graph
+    # replay (no per-launch events possible) in two extra steps afterwards
+    if not args.graph:
+        ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 1)
     ctx.kernel_timing()  # reset
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -134,6 +283,10 @@ def main():
     torch.cuda.synchronize()
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
+    if args.graph:
+        ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 1)
+        for _ in range(2):
+            ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
     n_launch, k_ms, k_bytes = ctx.kernel_timing()
     ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 0)
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, iters {iters}")
@@ -186,7 +339,8 @@ def main():
         "config": {
             "workload": (f"{pr.name}: {'3-D' if pr.mesh.dim == 3 else '2-D'} polytopal mesh, {pr.n_elem} elements, "
                          f"p={pr.p}, {pr.n_dof} dofs, {pr.n_sub} subdomains + P1 coarse, "
-                         f"Schwarz {pr.local_prec}/{pr.coarse_prec}, relres {pr.tol:g}"),
+                         f"Schwarz {pr.local_prec}/{pr.coarse_prec}, relres {pr.tol:g}"
+                         f"{', graph replay' if args.graph else ''}"),
             "n_dof": pr.n_dof, "n_elem": pr.n_elem, "p": pr.p, "n_sub": pr.n_sub,
         },
         "pcg_iters": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},

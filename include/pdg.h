@@ -102,6 +102,20 @@ typedef struct {
 
 pdg_status pdg_set_mesh(pdg_ctx *ctx, const pdg_mesh *mesh, int32_t p);
 
+/* Batch of independent systems (the batching form; not part of the paper).
+ * A context may hold several independent problems of the same degree p: their
+ * meshes are concatenated into the one mesh given to pdg_set_mesh, and the
+ * elements of system s are the contiguous run [elem_ptr[s], elem_ptr[s+1])
+ * (elem_ptr: host array of n_sys + 1 entries, from 0 to n_elem).  No facet may
+ * join two systems, and no subdomain or coarse element may span two.  Each
+ * system runs its own PCG (own alpha, beta, and stopping test on its own
+ * ||b_s||) inside shared kernel launches; every system gets the bits it would
+ * get in a context of its own.  The coarse level gets one dense K_0 per system.
+ * Default: one system.  Call after pdg_set_mesh, before
+ * pdg_setup_preconditioner.  Errors: PDG_EINVAL (ranges, a facet between
+ * systems), PDG_ESTATE (order). */
+pdg_status pdg_set_systems(pdg_ctx *ctx, int32_t n_sys, const int64_t *elem_ptr);
+
 /* Sizes after pdg_set_mesh (any pointer may be NULL). */
 pdg_status pdg_get_sizes(const pdg_ctx *ctx, int64_t *n_elem, int32_t *nd, int64_t *n_dof,
                          int64_t *nnz_blocks);
@@ -158,7 +172,9 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *ctx, const pdg_precond_desc *desc);
 
 /* Host copy of the FP64 inverse of subdomain `sub`'s matrix as a dense
  * [n_i][n_i] array (dofs in element-label order), and of the coarse operator:
- * P [n_elem][nd][nq0] and K_0 [N0][N0].  Sizes via pdg_get_precond_sizes. */
+ * P [n_elem][nd][nq0] and K_0 [N0][N0] (N0 = n_coarse * nq0, indexed by the
+ * caller's coarse labels; block diagonal over the systems of a batch).  Sizes
+ * via pdg_get_precond_sizes. */
 pdg_status pdg_get_precond_sizes(const pdg_ctx *ctx, int32_t sub, int64_t *n_i, int64_t *n0,
                                  int32_t *nq0);
 pdg_status pdg_get_local_inverse(const pdg_ctx *ctx, int32_t sub, double *out);
@@ -177,8 +193,12 @@ typedef enum {
     PDG_OPT_TRUE_RESIDUAL = 1,  /* 1: pdg_solve/pdg_step compute ||b - Kx||/||b|| (one extra SpMV) */
     PDG_OPT_CHUNK = 2,          /* PCG iterations launched between host convergence polls (>= 1) */
     PDG_OPT_KERNEL_TIMING = 3,  /* 1: time every Schwarz-apply launch with HIP events */
-    PDG_OPT_SCHWARZ_ITEM_KB = 4 /* target tile bytes (KiB) per Schwarz work item, 32..8192,
+    PDG_OPT_SCHWARZ_ITEM_KB = 4,/* target tile bytes (KiB) per Schwarz work item, 32..8192,
                                    default 256; set before pdg_setup_preconditioner */
+    PDG_OPT_GRAPH = 5,          /* 1: replay each chunk of PCG iterations as a captured HIP graph
+                                   (captured on first use; not while kernel timing is on);
+                                   needs a non-NULL stream in pdg_create (else PDG_EINVAL) */
+    PDG_OPT_SPMV_WAVES = 6      /* wavefronts per SpMV block-row group: 1, 2, 4 (default) or 8 */
 } pdg_option;
 pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 
@@ -187,6 +207,21 @@ pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
  * Synchronises the stream. */
 pdg_status pdg_kernel_timing(pdg_ctx *ctx, int64_t *launches, double *total_ms,
                              double *bytes_per_launch);
+
+/* Autotuner: times the Schwarz apply for work items of 64, 128, 256, 512 and
+ * 1024 KiB of tiles (those whose items fit in 64 KiB of LDS) and the SpMV
+ * with 1, 2, 4 and 8 wavefronts per block-row group, `reps` launches each
+ * (1..1000), with HIP events on the context's stream, and keeps the fastest
+ * of each.  Results do not change (only the work split and the summation
+ * order of the Schwarz partials do).  Synchronises.  Call after
+ * pdg_bind_workspace. */
+typedef struct {
+    int32_t item_kb;      /* chosen Schwarz work-item size (KiB) */
+    int32_t spmv_waves;   /* chosen wavefronts per SpMV group */
+    double schwarz_us;    /* mean Schwarz-apply kernel time at the choice */
+    double spmv_us;       /* mean SpMV kernel time at the choice */
+} pdg_tune_result;
+pdg_status pdg_autotune(pdg_ctx *ctx, int32_t reps, pdg_tune_result *out);
 
 /* ------------------------------------------------------------------------
  * 4. Compute calls (device pointers, [n_elem][nd] coefficient vectors).
@@ -226,6 +261,26 @@ pdg_status pdg_solve(pdg_ctx *ctx, const double *rhs, double *x, double tol, int
  * f_ext nullable.  Synchronises the stream. */
 pdg_status pdg_step(pdg_ctx *ctx, double *u, double *u_prev, double *ions, const double *f_ext,
                     double tol, int32_t maxit, pdg_solve_info *info);
+
+/* For a context holding a batch (pdg_set_systems) the info of pdg_solve /
+ * pdg_step summarises all systems: the largest iteration count and relative
+ * residuals, and bnorm over all systems; the call returns the first non-OK
+ * system status.  This returns system `sys`'s own info of the last solve or
+ * step, and its status (a pdg_status value) in *status (either may be NULL). */
+pdg_status pdg_get_system_info(const pdg_ctx *ctx, int32_t sys, pdg_solve_info *info,
+                               int32_t *status);
+
+/* pdg_step for n_ctx distinct contexts at once (e.g. one context per
+ * polynomial degree of a batch, each on its own stream): every context's
+ * chunk of PCG iterations is queued before the host waits on any of them, so
+ * the contexts' launches overlap.  u, u_prev, ions: host arrays of n_ctx
+ * device pointers; f_ext: NULL or n_ctx device pointers (entries may be NULL);
+ * info: NULL or n_ctx entries.  Every context is completed; returns the first
+ * non-OK status, with the message in pdg_last_error(ctxs[0]). */
+pdg_status pdg_step_batch(pdg_ctx *const *ctxs, int32_t n_ctx, double *const *u,
+                          double *const *u_prev, double *const *ions,
+                          const double *const *f_ext, double tol, int32_t maxit,
+                          pdg_solve_info *info);
 
 #ifdef __cplusplus
 }

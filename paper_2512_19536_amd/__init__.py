@@ -5,6 +5,6 @@ The compute path is libpdg.so (hand-written HIP kernels + C++ setup) behind the
 C-ABI in include/pdg.h; this package only marshals arguments to it.
 """
 from ._lib import EXPORTS, PdgError, load  # noqa: F401
-from .solver import Context, from_problem, initial_state  # noqa: F401
+from .solver import BatchSolver, Context, from_problem, initial_state, step_batch  # noqa: F401
 
 __all__ = ["Context", "from_problem", "initial_state", "PdgError", "load", "EXPORTS"]

@@ -18,15 +18,17 @@ PDG_OK, PDG_EINVAL, PDG_ENOMEM, PDG_EHIP, PDG_ENOTSPD, PDG_ENOCONV, PDG_EBREAKDO
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PDG_F64, PDG_F32, PDG_BF16 = 0, 1, 2
 PDG_OPT_TRUE_RESIDUAL, PDG_OPT_CHUNK, PDG_OPT_KERNEL_TIMING, PDG_OPT_SCHWARZ_ITEM_KB = 1, 2, 3, 4
+PDG_OPT_GRAPH, PDG_OPT_SPMV_WAVES = 5, 6
 PRECISIONS = {"f64": PDG_F64, "f32": PDG_F32, "bf16": PDG_BF16}
 
 #: every symbol declared in include/pdg.h
 EXPORTS = (
-    "pdg_create", "pdg_destroy", "pdg_last_error", "pdg_status_string", "pdg_set_mesh", "pdg_get_sizes",
+    "pdg_create", "pdg_destroy", "pdg_last_error", "pdg_status_string", "pdg_set_mesh", "pdg_set_systems",
+    "pdg_get_sizes",
     "pdg_assemble", "pdg_get_matrix", "pdg_set_ionic", "pdg_setup_preconditioner", "pdg_get_precond_sizes",
     "pdg_get_local_inverse", "pdg_get_coarse", "pdg_workspace_query", "pdg_bind_workspace", "pdg_set_option",
     "pdg_kernel_timing", "pdg_project_p0", "pdg_spmv", "pdg_precond_apply", "pdg_ionic", "pdg_rhs",
-    "pdg_solve", "pdg_step",
+    "pdg_solve", "pdg_step", "pdg_get_system_info", "pdg_step_batch", "pdg_autotune",
 )
 
 
@@ -46,6 +48,14 @@ class PdgSolveInfo(ctypes.Structure):
 
     def as_dict(self):
         return {"iters": self.iters, "relres": self.relres, "true_relres": self.true_relres, "bnorm": self.bnorm}
+
+
+class PdgTuneResult(ctypes.Structure):
+    _fields_ = [("item_kb", c_int32), ("spmv_waves", c_int32), ("schwarz_us", c_double), ("spmv_us", c_double)]
+
+    def as_dict(self):
+        return {"item_kb": self.item_kb, "spmv_waves": self.spmv_waves, "schwarz_us": self.schwarz_us,
+                "spmv_us": self.spmv_us}
 
 
 class PdgError(RuntimeError):
@@ -72,6 +82,7 @@ def load():
         "pdg_last_error": (c_char_p, [V]),
         "pdg_status_string": (c_char_p, [I32]),
         "pdg_set_mesh": (I32, [V, POINTER(PdgMesh), I32]),
+        "pdg_set_systems": (I32, [V, I32, P]),
         "pdg_get_sizes": (I32, [V, P, P, P, P]),
         "pdg_assemble": (I32, [V, D, D, D, D]),
         "pdg_get_matrix": (I32, [V, P, P, P, P]),
@@ -91,6 +102,9 @@ def load():
         "pdg_rhs": (I32, [V, P, P, P, P]),
         "pdg_solve": (I32, [V, P, P, D, I32, POINTER(PdgSolveInfo)]),
         "pdg_step": (I32, [V, P, P, P, P, D, I32, POINTER(PdgSolveInfo)]),
+        "pdg_get_system_info": (I32, [V, I32, POINTER(PdgSolveInfo), POINTER(I32)]),
+        "pdg_step_batch": (I32, [P, I32, P, P, P, P, D, I32, P]),
+        "pdg_autotune": (I32, [V, I32, POINTER(PdgTuneResult)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

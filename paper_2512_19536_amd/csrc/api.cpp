@@ -51,6 +51,26 @@ struct Layout {
     }
 };
 
+// Workspace slots (indices into Layout::items).
+struct Ws {
+    int grows, gslot, gcol, gval, gsys, mass, minv, qpptr, qpxi, qpw, norm, prm, subptr, subel;
+    int itsys, itrow, itj0, itnj, itown, rtit0, dofrt, itdot, rowpart;
+    int sysn, sysnt, systoff, sysdof0, syscb, rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
+    int grpptr, grpel, upsys, cchunk, csys0, crt0, rspmv, rupd, ritem, rowner;
+    int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
+};
+
+// State of the PCG run in progress (between pcg_begin and pcg_end).
+struct PcgRun {
+    double *x = nullptr;        // caller's iterate (written at the end)
+    const double *b = nullptr;  // right-hand side kept for the true residual
+    bool step = false;
+    int maxit = 0;
+    int j = 1;                  // next iteration to launch
+    int next = 1;               // iterations to launch before the next poll
+    bool active = false;
+};
+
 }  // namespace
 
 struct pdg_ctx {
@@ -60,7 +80,7 @@ struct pdg_ctx {
     std::string err;
     int n_threads = 0;
     // options
-    int true_resid = 0, chunk = 4, timing = 0, item_kb = 256;
+    int true_resid = 0, chunk = 4, timing = 0, item_kb = 256, use_graph = 0, spmv_wpg = 4;
     int prev_iters = 0;
     // host data
     Mesh mesh;
@@ -70,45 +90,39 @@ struct pdg_ctx {
     std::vector<double> ionic;
     bool has_ionic = false;
     Precond pc;
-    std::vector<int32_t> grp_ptr, grp_elems;  // update chunks (element runs inside one coarse element)
-    std::vector<int32_t> cchunk_ptr;          // [n_coarse+1] chunks of each coarse element
-    // Schwarz work items
-    std::vector<int32_t> it_sys, it_row, it_j0, it_nj, it_rt, rt_item0;
+    // batch of independent systems: system s owns elements [sys_elem_ptr[s], sys_elem_ptr[s+1])
+    int n_sys = 1;
+    std::vector<int64_t> sys_elem_ptr;
+    std::vector<int32_t> elem_sys;
+    // per-system ranges of the partial producers
+    std::vector<int32_t> r_spmv, r_upd, r_item, r_owner;
+    // update chunks (element runs inside one coarse element)
+    std::vector<int32_t> grp_ptr, grp_elems, upd_sys, cchunk_ptr;
+    // Schwarz work items and tile rows
+    std::vector<int32_t> it_sys, it_row, it_j0, it_nj, it_own, rt_item0, rt_k, rt_nt, dof_rt, coarse_rt0;
+    std::vector<int64_t> rt_cbase;
     int max_nj = 1;
+    int64_t items_reserved = 0;
     // group-ELL matrix (host staging)
     int G = 1;
     int64_t n_groups = 0, n_slots = 0;
-    std::vector<int32_t> grp_rows, grp_col;
+    std::vector<int32_t> grp_rows, grp_col, grp_sys;
     std::vector<int64_t> grp_slot_off;
     std::vector<double> grp_val;
     // device
     Layout lay;
+    Ws w{};
     char *ws = nullptr;
     size_t ws_bytes = 0;
     DevMatrix dA{};
     DevScalars *sc = nullptr, *sc_apply = nullptr, *sc_host = nullptr;
-    int64_t *d_qp_ptr = nullptr;
-    double *d_qp_xi = nullptr, *d_qp_w = nullptr, *d_norm = nullptr, *d_minv = nullptr, *d_prm = nullptr;
-    int32_t *d_sub_ptr = nullptr, *d_sub_elems = nullptr;
-    int32_t *d_sys_n = nullptr, *d_sys_nt = nullptr, *d_elem_coarse = nullptr;
-    int32_t *d_grp_ptr = nullptr, *d_grp_elems = nullptr, *d_cchunk_ptr = nullptr;
-    int32_t *d_it_sys = nullptr, *d_it_row = nullptr, *d_it_j0 = nullptr, *d_it_nj = nullptr, *d_it_rt = nullptr,
-            *d_rt_item0 = nullptr;
-    int32_t *d_dof_rt = nullptr;
-    double *d_part = nullptr, *d_r0part = nullptr, *d_itemdot = nullptr, *d_spart = nullptr, *d_rrpart = nullptr;
-    std::vector<int32_t> dof_rt;
-    int coarse_rt0 = -1;
-    int64_t *d_sys_toff = nullptr, *d_sys_dof0 = nullptr, *d_sys_cbase = nullptr, *d_rt_cbase = nullptr;
-    int32_t *d_rt_k = nullptr, *d_rt_nt = nullptr;
-    double *d_colpart = nullptr;
-    std::vector<int32_t> rt_k, rt_nt;
-    std::vector<int64_t> rt_cbase;
-    void *d_tiles_local = nullptr, *d_tiles_coarse = nullptr;
-    double *d_P = nullptr;
-    double *v_r = nullptr, *v_z = nullptr, *v_p = nullptr, *v_q = nullptr, *v_I = nullptr, *v_t = nullptr,
-           *v_b = nullptr, *v_z0 = nullptr;
-    int max_sys_n = 0;
     int64_t schwarz_bytes = 0;
+    PcgRun run;
+    std::vector<DevScalars> last;       // per-system scalars of the last solve
+    std::vector<double> last_true;      // per-system true relative residual (-1 if not computed)
+    // graph of one chunk of PCG iterations
+    hipGraphExec_t gexec = nullptr;
+    int gexec_chunk = 0;
     // kernel timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     size_t ev_used = 0;
@@ -118,11 +132,11 @@ struct pdg_ctx {
 
 namespace {
 
-void require(pdg_ctx *c, int st, const char *what) {
+void require(const pdg_ctx *c, int st, const char *what) {
     if (!c) throw Error(PDG_EINVAL, "ctx is NULL");
     if (c->state < st) throw Error(PDG_ESTATE, std::string(what) + ": call out of order");
 }
-void require_gpu(pdg_ctx *c) {
+void require_gpu(const pdg_ctx *c) {
     require(c, S_BOUND, "compute call");
     if (c->device < 0) throw Error(PDG_ESTATE, "host-only context");
 }
@@ -145,6 +159,14 @@ pdg_status guard(pdg_ctx *c, F f) {
     }
 }
 
+void drop_graph(pdg_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gexec_chunk = 0;
+}
+
+// Group-ELL form of K: element rows sorted by (system, neighbour count
+// descending), cut into groups of G rows that never straddle two systems.
 void build_group_ell(pdg_ctx *c) {
     const int nd = c->mesh.nd;
     const int64_t n = c->K.n_rows;
@@ -153,18 +175,28 @@ void build_group_ell(pdg_ctx *c) {
     std::vector<int32_t> perm(n);
     std::iota(perm.begin(), perm.end(), 0);
     auto nb = [&](int32_t r) { return c->K.row_ptr[r + 1] - c->K.row_ptr[r]; };
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return nb(a) > nb(b); });
-    c->n_groups = (n + G - 1) / G;
-    c->grp_rows.assign(c->n_groups * G, -1);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+        if (c->elem_sys[a] != c->elem_sys[b]) return c->elem_sys[a] < c->elem_sys[b];
+        return nb(a) > nb(b);
+    });
+    c->grp_rows.clear();
+    c->grp_sys.clear();
+    c->r_spmv.assign(c->n_sys + 1, 0);
+    for (int b = 0; b < c->n_sys; ++b) {
+        const int64_t r0 = c->sys_elem_ptr[b], r1 = c->sys_elem_ptr[b + 1];  // rows of b are contiguous in perm
+        for (int64_t k = r0; k < r1; k += G) {
+            for (int r = 0; r < G; ++r) c->grp_rows.push_back(k + r < r1 ? perm[k + r] : -1);
+            c->grp_sys.push_back(b);
+        }
+        c->r_spmv[b + 1] = (int32_t)c->grp_sys.size();
+    }
+    c->n_groups = (int64_t)c->grp_sys.size();
     c->grp_slot_off.assign(c->n_groups + 1, 0);
     for (int64_t g = 0; g < c->n_groups; ++g) {
         int64_t smax = 0;
         for (int r = 0; r < G; ++r) {
-            int64_t k = g * G + r;
-            if (k < n) {
-                c->grp_rows[k] = perm[k];
-                smax = std::max<int64_t>(smax, nb(perm[k]));
-            }
+            const int32_t row = c->grp_rows[g * G + r];
+            if (row >= 0) smax = std::max<int64_t>(smax, nb(row));
         }
         c->grp_slot_off[g + 1] = c->grp_slot_off[g] + smax;
     }
@@ -193,69 +225,183 @@ void build_group_ell(pdg_ctx *c) {
     }
 }
 
-size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32 ? 4 : 2); }
+// Update chunks: runs of at most 32 elements inside one coarse element (or
+// inside one system without a coarse level), in system order.
+void plan_chunks(pdg_ctx *c) {
+    constexpr int kChunk = 32;
+    const Precond &pc = c->pc;
+    c->grp_ptr.assign(1, 0);
+    c->grp_elems.clear();
+    c->upd_sys.clear();
+    c->cchunk_ptr.assign(1, 0);
+    auto add_run = [&](const int32_t *el, int64_t cnt, int b) {
+        for (int64_t e = 0; e < cnt; e += kChunk) {
+            for (int64_t k = e; k < std::min<int64_t>(cnt, e + kChunk); ++k) c->grp_elems.push_back(el[k]);
+            c->grp_ptr.push_back((int32_t)c->grp_elems.size());
+            c->upd_sys.push_back(b);
+        }
+    };
+    if (pc.q > 0) {
+        for (int cc = 0; cc < pc.n_coarse; ++cc) {
+            const int a0 = pc.coarse_ptr[cc], a1 = pc.coarse_ptr[cc + 1];
+            add_run(&pc.coarse_elems[a0], a1 - a0, c->elem_sys[pc.coarse_elems[a0]]);
+            c->cchunk_ptr.push_back((int32_t)c->grp_ptr.size() - 1);
+        }
+    } else {
+        std::vector<int32_t> el(c->mesh.n_elem);
+        std::iota(el.begin(), el.end(), 0);
+        for (int b = 0; b < c->n_sys; ++b)
+            add_run(&el[c->sys_elem_ptr[b]], c->sys_elem_ptr[b + 1] - c->sys_elem_ptr[b], b);
+    }
+    c->r_upd.assign(c->n_sys + 1, 0);
+    for (int32_t b : c->upd_sys) c->r_upd[b + 1]++;
+    for (int b = 0; b < c->n_sys; ++b) c->r_upd[b + 1] += c->r_upd[b];
+}
 
-enum WsItem {
-    W_GROWS, W_GSLOT, W_GCOL, W_GVAL, W_MASS, W_MINV, W_QPPTR, W_QPXI, W_QPW, W_NORM, W_PRM,
-    W_SUBPTR, W_SUBEL, W_ITSYS, W_ITROW, W_ITJ0, W_ITNJ, W_ITRT, W_RTIT0, W_DOFRT, W_ITDOT, W_SPART,
-    W_SYSN, W_SYSNT, W_SYSTOFF, W_SYSDOF0, W_SYSCB, W_RTK, W_RTNT, W_RTCB, W_COLP, W_TLOC, W_TCOA, W_P, W_ECOA, W_GRPPTR, W_GRPEL, W_CCHUNK,
-    W_R, W_Z, W_PV, W_Q, W_I, W_T, W_B, W_R0P, W_Z0, W_SC, W_SCA, W_PART, W_RRPART, W_COUNT
-};
+size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32 ? 4 : 2); }
+int store_kind(int prec) { return prec == PDG_F64 ? STORE_F64 : (prec == PDG_F32 ? STORE_F32 : STORE_BF16); }
+
+// Schwarz work items for a target of `kb` KiB of tiles per item: the stored
+// tiles (I, J <= I) of each packed tile row, split into even runs.  Order: per
+// batch system its subdomains (ascending), then its coarse system, so each
+// system's items (and tile rows) are one contiguous range.  With count_only
+// set, returns the item count and changes nothing.
+int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
+    const Precond &pc = c->pc;
+    const int nd = c->mesh.nd;
+    std::vector<std::vector<int>> subs(c->n_sys);
+    for (int s = 0; s < pc.n_sub; ++s) subs[pc.sub_bsys[s]].push_back(s);
+    int64_t count = 0;
+    if (!count_only) {
+        c->it_sys.clear(); c->it_row.clear(); c->it_j0.clear(); c->it_nj.clear(); c->it_own.clear();
+        c->rt_item0.assign(1, 0);
+        c->rt_k.clear(); c->rt_nt.clear(); c->rt_cbase.clear();
+        c->coarse_rt0.assign(c->n_sys, 0);
+        c->r_item.assign(c->n_sys + 1, 0);
+        c->max_nj = 1;
+    }
+    std::vector<int32_t> rt0_of_sub(pc.n_sub, 0);
+    int32_t n_rt = 0;
+    auto add_sys = [&](int sidx, int b) {
+        const int64_t nt = pc.sys[sidx].nt;
+        const int prec = sidx < pc.n_sub ? pc.local_prec : pc.coarse_prec;
+        const int64_t jc = std::max<int64_t>(1, ((int64_t)kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
+        for (int64_t I = 0; I < nt; ++I) {
+            const int64_t ntile = I + 1, nc = (ntile + jc - 1) / jc;
+            count += nc;
+            ++n_rt;
+            if (count_only) continue;
+            for (int64_t k = 0; k < nc; ++k) {
+                const int64_t j0 = k * ntile / nc, j1 = (k + 1) * ntile / nc;
+                c->it_sys.push_back(sidx);
+                c->it_row.push_back((int32_t)I);
+                c->it_j0.push_back((int32_t)j0);
+                c->it_nj.push_back((int32_t)(j1 - j0));
+                c->it_own.push_back(b);
+                c->max_nj = std::max<int>(c->max_nj, (int)(j1 - j0));
+            }
+            c->rt_item0.push_back((int32_t)c->it_sys.size());
+            c->rt_k.push_back((int32_t)I);
+            c->rt_nt.push_back((int32_t)nt);
+            c->rt_cbase.push_back(pc.sys[sidx].tile_off);
+        }
+    };
+    for (int b = 0; b < c->n_sys; ++b) {
+        for (int s : subs[b]) {
+            rt0_of_sub[s] = n_rt;
+            add_sys(s, b);
+        }
+        if (pc.q > 0) {
+            if (!count_only) c->coarse_rt0[b] = n_rt;
+            add_sys(pc.n_sub + b, b);
+        }
+        if (!count_only) c->r_item[b + 1] = (int32_t)c->it_sys.size();
+    }
+    if (count_only) return count;
+    // tile row (and row inside it) of every fine dof, for assembling z
+    c->dof_rt.assign(c->mesh.n_elem * nd, 0);
+    for (int s = 0; s < pc.n_sub; ++s) {
+        const int a0 = pc.sub_ptr[s], a1 = pc.sub_ptr[s + 1];
+        for (int le = 0; le < a1 - a0; ++le)
+            for (int i = 0; i < nd; ++i) {
+                const int pos = le * nd + i;
+                c->dof_rt[(int64_t)pc.sub_elems[a0 + le] * nd + i] = (rt0_of_sub[s] + pos / kTile) * kTile + pos % kTile;
+            }
+    }
+    return count;
+}
 
 void plan_layout(pdg_ctx *c) {
     const int64_t n = c->mesh.n_elem, nd = c->mesh.nd, N = n * nd, nq = c->mesh.qp_ptr[n];
     const Precond &pc = c->pc;
-    const int64_t n_sys = (int64_t)pc.sys.size();
+    const int64_t n_dsys = (int64_t)pc.sys.size(), n_rt = (int64_t)c->rt_item0.size() - 1;
+    const int64_t n_items = c->items_reserved, n_sys = c->n_sys;
     int64_t local_tiles = 0, coarse_tiles = 0;
-    for (int s = 0; s < pc.n_sub; ++s) local_tiles += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
-    if (pc.q > 0) coarse_tiles = pc.sys[pc.n_sub].nt * (pc.sys[pc.n_sub].nt + 1) / 2;
-    const int64_t N0 = std::max<int64_t>(1, pc.N0);
-    int64_t max_grid = std::max<int64_t>({(int64_t)spmv_blocks(DevMatrix{(int)nd, c->G, n, c->n_groups}),
-                                          (int64_t)c->grp_ptr.size(), 1});
-    const int64_t n_items = (int64_t)c->it_sys.size(), n_rt = (int64_t)c->rt_item0.size() - 1;
+    for (int64_t s = 0; s < n_dsys; ++s) (s < pc.n_sub ? local_tiles : coarse_tiles) += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
+    const int64_t n_chunks = (int64_t)c->grp_ptr.size() - 1;
     Layout &L = c->lay;
     L = Layout();
-    L.add(c->grp_rows.size() * 4);
-    L.add(c->grp_slot_off.size() * 8);
-    L.add(c->grp_col.size() * 4);
-    L.add(c->grp_val.size() * 8);
-    L.add(N * nd * 8);
-    L.add(N * nd * 8);
-    L.add((n + 1) * 8);
-    L.add(nq * c->mesh.dim * 8);
-    L.add(nq * 8);
-    L.add(N * 8);
-    L.add(kIonicParams * 8);
-    L.add(pc.sub_ptr.size() * 4);
-    L.add(pc.sub_elems.size() * 4);
-    for (int k = 0; k < 5; ++k) L.add(n_items * 4);   // item sys/row/j0/nj/rt
-    L.add((n_rt + 1) * 4);
-    L.add(N * 4);
-    L.add(n_items * 8);
-    L.add(n_items * kTile * 8);
-    L.add(n_sys * 4);
-    L.add(n_sys * 4);
-    L.add(n_sys * 8);
-    L.add(n_sys * 8);
-    L.add(n_sys * 8);
-    L.add(n_rt * 4);
-    L.add(n_rt * 4);
-    L.add(n_rt * 8);
-    L.add((local_tiles + coarse_tiles) * kTile * 8);
-    L.add(local_tiles * kTile * kTile * tile_elem_bytes(pc.local_prec));
-    L.add(coarse_tiles * kTile * kTile * tile_elem_bytes(pc.coarse_prec));
-    L.add(pc.P.size() * 8);
-    L.add(pc.elem_coarse.size() * 4);
-    L.add(c->grp_ptr.size() * 4);
-    L.add(c->grp_elems.size() * 4);
-    L.add(c->cchunk_ptr.size() * 4);
-    for (int k = 0; k < 7; ++k) L.add(N * 8);  // r z p q I t b
-    L.add(std::max<int64_t>(1, (int64_t)c->grp_ptr.size() * std::max(pc.nq0, 1)) * 8);  // r0 shares per chunk
-    L.add(N0 * 8);
-    L.add(sizeof(DevScalars));
-    L.add(sizeof(DevScalars));
-    L.add(std::max<int64_t>(1, c->n_groups) * 2 * 8);   // SpMV partials
-    L.add(std::max<int64_t>(1, (int64_t)c->grp_ptr.size()) * 8);  // update partials
+    Ws &w = c->w;
+    w.grows = L.add(c->grp_rows.size() * 4);
+    w.gslot = L.add(c->grp_slot_off.size() * 8);
+    w.gcol = L.add(c->grp_col.size() * 4);
+    w.gval = L.add(c->grp_val.size() * 8);
+    w.gsys = L.add(c->grp_sys.size() * 4);
+    w.mass = L.add(N * nd * 8);
+    w.minv = L.add(N * nd * 8);
+    w.qpptr = L.add((n + 1) * 8);
+    w.qpxi = L.add(nq * c->mesh.dim * 8);
+    w.qpw = L.add(nq * 8);
+    w.norm = L.add(N * 8);
+    w.prm = L.add(kIonicParams * 8);
+    w.subptr = L.add(pc.sub_ptr.size() * 4);
+    w.subel = L.add(pc.sub_elems.size() * 4);
+    w.itsys = L.add(n_items * 4);
+    w.itrow = L.add(n_items * 4);
+    w.itj0 = L.add(n_items * 4);
+    w.itnj = L.add(n_items * 4);
+    w.itown = L.add(n_items * 4);
+    w.rtit0 = L.add((n_rt + 1) * 4);
+    w.dofrt = L.add(N * 4);
+    w.itdot = L.add(n_items * 8);
+    w.rowpart = L.add(n_items * kTile * 8);
+    w.sysn = L.add(n_dsys * 4);
+    w.sysnt = L.add(n_dsys * 4);
+    w.systoff = L.add(n_dsys * 8);
+    w.sysdof0 = L.add(n_dsys * 8);
+    w.syscb = L.add(n_dsys * 8);
+    w.rtk = L.add(n_rt * 4);
+    w.rtnt = L.add(n_rt * 4);
+    w.rtcb = L.add(n_rt * 8);
+    w.colp = L.add((local_tiles + coarse_tiles) * kTile * 8);
+    w.tloc = L.add(local_tiles * kTile * kTile * tile_elem_bytes(pc.local_prec));
+    w.tcoa = L.add(coarse_tiles * kTile * kTile * tile_elem_bytes(pc.coarse_prec));
+    w.P = L.add(pc.P.size() * 8);
+    w.ecoa = L.add(pc.elem_coarse.size() * 4);
+    w.elsys = L.add(n * 4);
+    w.grpptr = L.add(c->grp_ptr.size() * 4);
+    w.grpel = L.add(c->grp_elems.size() * 4);
+    w.upsys = L.add(c->upd_sys.size() * 4);
+    w.cchunk = L.add(c->cchunk_ptr.size() * 4);
+    w.csys0 = L.add((n_sys + 1) * 4);
+    w.crt0 = L.add(n_sys * 4);
+    w.rspmv = L.add((n_sys + 1) * 4);
+    w.rupd = L.add((n_sys + 1) * 4);
+    w.ritem = L.add((n_sys + 1) * 4);
+    w.rowner = L.add(n_sys * 4);
+    w.x = L.add(N * 8);
+    w.r = L.add(N * 8);
+    w.z = L.add(N * 8);
+    w.p = L.add(N * 8);
+    w.q = L.add(N * 8);
+    w.I = L.add(N * 8);
+    w.t = L.add(N * 8);
+    w.b = L.add(N * 8);
+    w.r0p = L.add(std::max<int64_t>(1, n_chunks * std::max(pc.nq0, 1)) * 8);
+    w.sc = L.add(n_sys * sizeof(DevScalars));
+    w.sca = L.add(n_sys * sizeof(DevScalars));
+    w.part = L.add(std::max<int64_t>(1, c->n_groups) * 2 * 8);  // SpMV partials
+    w.rrpart = L.add(std::max<int64_t>(1, n_chunks) * 8);       // update partials
 }
 
 template <class T>
@@ -264,8 +410,21 @@ T *wptr(pdg_ctx *c, int item) { return reinterpret_cast<T *>(c->ws + c->lay.item
 template <class T>
 void upload(pdg_ctx *c, int item, const std::vector<T> &v) {
     if (v.empty()) return;
+    if (v.size() * sizeof(T) > c->lay.items[item].bytes) throw Error(PDG_EINVAL, "internal: upload exceeds its slot");
     HIPCHK(hipMemcpyAsync(c->ws + c->lay.items[item].off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice,
                           c->stream));
+}
+
+void upload_items(pdg_ctx *c) {
+    if ((int64_t)c->it_sys.size() > c->items_reserved) throw Error(PDG_EINVAL, "internal: item plan exceeds its slot");
+    upload(c, c->w.itsys, c->it_sys);
+    upload(c, c->w.itrow, c->it_row);
+    upload(c, c->w.itj0, c->it_j0);
+    upload(c, c->w.itnj, c->it_nj);
+    upload(c, c->w.itown, c->it_own);
+    upload(c, c->w.rtit0, c->rt_item0);
+    upload(c, c->w.ritem, c->r_item);
+    HIPCHK(hipStreamSynchronize(c->stream));
 }
 
 pdg_status map_status(int st) {
@@ -279,7 +438,15 @@ pdg_status map_status(int st) {
     }
 }
 
-int store_kind(int prec) { return prec == PDG_F64 ? STORE_F64 : (prec == PDG_F32 ? STORE_F32 : STORE_BF16); }
+SysRanges ranges(pdg_ctx *c) {
+    SysRanges r{};
+    r.n_sys = c->n_sys;
+    r.spmv = wptr<int32_t>(c, c->w.rspmv);
+    r.upd = wptr<int32_t>(c, c->w.rupd);
+    r.item = wptr<int32_t>(c, c->w.ritem);
+    r.owner = wptr<int32_t>(c, c->w.rowner);
+    return r;
+}
 
 SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) {
     SchwarzArgs a{};
@@ -287,27 +454,34 @@ SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) 
     a.nd = c->mesh.nd;
     a.n_sub = c->pc.n_sub;
     a.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
-    a.item_sys = c->d_it_sys;
-    a.item_row = c->d_it_row;
-    a.item_j0 = c->d_it_j0;
-    a.item_nj = c->d_it_nj;
-    a.part = c->d_part;
-    a.itemdot = c->d_itemdot;
-    a.sys_n = c->d_sys_n;
-    a.sys_nt = c->d_sys_nt;
-    a.sys_toff = c->d_sys_toff;
-    a.sys_dof0 = c->d_sys_dof0;
-    a.sys_cbase = c->d_sys_cbase;
-    a.colpart = c->d_colpart;
-    a.tiles_local = c->d_tiles_local;
-    a.tiles_coarse = c->d_tiles_coarse;
-    a.sub_ptr = c->d_sub_ptr;
-    a.sub_elems = c->d_sub_elems;
-    a.cchunk_ptr = c->d_cchunk_ptr;
+    a.item_sys = wptr<int32_t>(c, c->w.itsys);
+    a.item_row = wptr<int32_t>(c, c->w.itrow);
+    a.item_j0 = wptr<int32_t>(c, c->w.itj0);
+    a.item_nj = wptr<int32_t>(c, c->w.itnj);
+    a.item_owner = wptr<int32_t>(c, c->w.itown);
+    a.part = wptr<double>(c, c->w.rowpart);
+    a.itemdot = wptr<double>(c, c->w.itdot);
+    a.colpart = wptr<double>(c, c->w.colp);
+    a.sys_n = wptr<int32_t>(c, c->w.sysn);
+    a.sys_nt = wptr<int32_t>(c, c->w.sysnt);
+    a.sys_toff = wptr<int64_t>(c, c->w.systoff);
+    a.sys_dof0 = wptr<int64_t>(c, c->w.sysdof0);
+    a.sys_cbase = wptr<int64_t>(c, c->w.syscb);
+    a.csys_ce0 = wptr<int32_t>(c, c->w.csys0);
+    a.tiles_local = wptr<void>(c, c->w.tloc);
+    a.tiles_coarse = wptr<void>(c, c->w.tcoa);
+    a.sub_ptr = wptr<int32_t>(c, c->w.subptr);
+    a.sub_elems = wptr<int32_t>(c, c->w.subel);
+    a.cchunk_ptr = wptr<int32_t>(c, c->w.cchunk);
     a.r = r;
-    a.r0part = c->d_r0part;
+    a.r0part = wptr<double>(c, c->w.r0p);
     a.sc = sc;
     return a;
+}
+
+void launch_schwarz_plain(pdg_ctx *c, const SchwarzArgs &a) {
+    HIPCHK(launch_schwarz(a, (int)c->it_sys.size(), store_kind(c->pc.local_prec), store_kind(c->pc.coarse_prec),
+                          c->max_nj, c->stream));
 }
 
 void launch_schwarz_timed(pdg_ctx *c, const SchwarzArgs &a) {
@@ -323,8 +497,7 @@ void launch_schwarz_timed(pdg_ctx *c, const SchwarzArgs &a) {
         e1 = c->ev_pool[c->ev_used].second;
         HIPCHK(hipEventRecord(e0, c->stream));
     }
-    HIPCHK(launch_schwarz(a, (int)c->it_sys.size(), store_kind(c->pc.local_prec),
-                          store_kind(c->pc.coarse_prec), c->max_nj, c->stream));
+    launch_schwarz_plain(c, a);
     if (c->timing) {
         HIPCHK(hipEventRecord(e1, c->stream));
         c->ev_used++;
@@ -344,73 +517,116 @@ void harvest_timing(pdg_ctx *c, size_t keep) {
     c->ev_used = 0;
 }
 
-UpdateArgs update_args(pdg_ctx *c, int init, int iter, double *x, double *r, DevScalars *sc) {
+UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *sc) {
     UpdateArgs u{};
     u.init = init;
-    u.iter = iter;
     u.nd = c->mesh.nd;
     u.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
-    u.grp_ptr = c->d_grp_ptr;
-    u.grp_elems = c->d_grp_elems;
+    u.grp_ptr = wptr<int32_t>(c, c->w.grpptr);
+    u.grp_elems = wptr<int32_t>(c, c->w.grpel);
+    u.grp_sys = wptr<int32_t>(c, c->w.upsys);
     u.n_grp = (int)c->grp_ptr.size() - 1;
     u.x = x;
     u.r = r;
-    u.p = c->v_p;
-    u.q = c->v_q;
-    u.P = c->d_P;
-    u.r0part = c->d_r0part;
-    u.pqpart = c->d_spart;
-    u.n_pq = (int)c->n_groups;
-    u.rrpart = c->d_rrpart;
+    u.p = wptr<double>(c, c->w.p);
+    u.q = wptr<double>(c, c->w.q);
+    u.P = c->pc.q > 0 ? wptr<double>(c, c->w.P) : nullptr;
+    u.r0part = wptr<double>(c, c->w.r0p);
+    u.pqpart = wptr<double>(c, c->w.part);
+    u.rrpart = wptr<double>(c, c->w.rrpart);
+    u.rng = ranges(c);
     u.sc = sc;
     return u;
 }
 
-PupdateArgs pupdate_args(pdg_ctx *c, int mode, int iter, double *out, DevScalars *sc) {
+PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
     PupdateArgs p{};
     p.mode = mode;
-    p.iter = iter;
     p.nd = c->mesh.nd;
     p.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
     p.n_elem = c->mesh.n_elem;
-    p.P = c->d_P;
-    p.elem_coarse = c->d_elem_coarse;
-    p.dof_rt = c->d_dof_rt;
-    p.rt_item0 = c->d_rt_item0;
-    p.rt_k = c->d_rt_k;
-    p.rt_nt = c->d_rt_nt;
-    p.rt_cbase = c->d_rt_cbase;
-    p.colpart = c->d_colpart;
-    p.coarse_rt0 = c->coarse_rt0;
-    p.part = c->d_part;
-    p.itemdot = c->d_itemdot;
-    p.n_items = (int)c->it_sys.size();
-    p.rrpart = c->d_rrpart;
-    p.n_rr = (int)c->grp_ptr.size() - 1;
-    p.bbpart = c->d_spart;
-    p.n_bb = (int)c->n_groups;
+    p.P = c->pc.q > 0 ? wptr<double>(c, c->w.P) : nullptr;
+    p.elem_coarse = c->pc.q > 0 ? wptr<int32_t>(c, c->w.ecoa) : nullptr;
+    p.elem_sys = wptr<int32_t>(c, c->w.elsys);
+    p.dof_rt = wptr<int32_t>(c, c->w.dofrt);
+    p.rt_item0 = wptr<int32_t>(c, c->w.rtit0);
+    p.rt_k = wptr<int32_t>(c, c->w.rtk);
+    p.rt_nt = wptr<int32_t>(c, c->w.rtnt);
+    p.rt_cbase = wptr<int64_t>(c, c->w.rtcb);
+    p.coarse_rt0 = wptr<int32_t>(c, c->w.crt0);
+    p.csys_ce0 = wptr<int32_t>(c, c->w.csys0);
+    p.part = wptr<double>(c, c->w.rowpart);
+    p.colpart = wptr<double>(c, c->w.colp);
+    p.itemdot = wptr<double>(c, c->w.itdot);
+    p.rrpart = wptr<double>(c, c->w.rrpart);
+    p.bbpart = wptr<double>(c, c->w.part);
+    p.rng = ranges(c);
     p.p = out;
     p.sc = sc;
     return p;
 }
 
-// PCG from x0 = x on K x = b.  step_mode: b is built from x (= U^k) and the
-// ion term, and u_prev receives U^k.
-pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u_prev, const double *f_ext,
-                   double tol, int maxit, pdg_solve_info *info) {
+double *vec(pdg_ctx *c, int item) { return wptr<double>(c, item); }
+
+// The four launches of one PCG iteration on the internal vectors (no
+// iteration index: the kernels take it from the device scalars).
+void launch_iteration(pdg_ctx *c, bool timed) {
+    hipStream_t s = c->stream;
+    SpmvArgs q{};
+    q.mode = SPMV_PQ;
+    q.x = vec(c, c->w.p);
+    q.y = vec(c, c->w.q);
+    q.part = vec(c, c->w.part);
+    q.sc = c->sc;
+    HIPCHK(launch_spmv(c->dA, q, s));
+    HIPCHK(launch_update(update_args(c, 0, vec(c, c->w.x), vec(c, c->w.r), c->sc), s));
+    if (timed) launch_schwarz_timed(c, schwarz_args(c, 2, vec(c, c->w.r), c->sc));
+    else launch_schwarz_plain(c, schwarz_args(c, 2, vec(c, c->w.r), c->sc));
+    HIPCHK(launch_pupdate(pupdate_args(c, 2, vec(c, c->w.p), c->sc), s));
+}
+
+// Captures one chunk of iterations as a graph (once per chunk length).
+void ensure_graph(pdg_ctx *c) {
+    if (c->gexec && c->gexec_chunk == c->chunk) return;
+    drop_graph(c);
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int k = 0; k < c->chunk; ++k) launch_iteration(c, false);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(c->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t er = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (er != hipSuccess) throw Error(PDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(er));
+    c->gexec = e;
+    c->gexec_chunk = c->chunk;
+}
+
+// PCG from x0 = x on K x = b for every system of the context: residual,
+// z0 = B r0, p0 = z0.  step_mode: b is built from x (= U^k) and the ion term,
+// and u_prev receives U^k.  Enqueue only.
+void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u_prev, const double *f_ext,
+               double tol, int maxit) {
     if (maxit < 0) throw Error(PDG_EINVAL, "maxit < 0");
     if (!(tol >= 0.0)) throw Error(PDG_EINVAL, "tol must be >= 0");
     hipStream_t s = c->stream;
     DevScalars *sc = c->sc;
-    HIPCHK(launch_status_reset(sc, tol * tol, maxit, 0, s));
+    HIPCHK(launch_status_reset(sc, c->n_sys, tol * tol, maxit, 0, s));
     SpmvArgs a{};
     a.x = x;
-    a.part = c->d_spart;
+    a.part = vec(c, c->w.part);
     a.sc = sc;
+    a.xcopy = vec(c, c->w.x);
+    a.y = vec(c, c->w.r);
     if (step_mode) {
         a.mode = SPMV_STEP;
-        a.y = c->v_r;
-        a.I = c->v_I;
+        a.I = vec(c, c->w.I);
         a.f = f_ext;
         a.u_prev = u_prev;
         a.two_c = 2.0 * c->c;
@@ -418,68 +634,144 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
         // b is kept for the optional true-residual check
         SpmvArgs rb = a;
         rb.mode = SPMV_RHS;
-        rb.y = c->v_b;
+        rb.y = vec(c, c->w.b);
+        rb.xcopy = nullptr;
         if (c->true_resid) HIPCHK(launch_spmv(c->dA, rb, s));
     } else {
         a.mode = SPMV_RESID;
         a.b = b;
-        a.y = c->v_r;
     }
     HIPCHK(launch_spmv(c->dA, a, s));
-    HIPCHK(launch_update(update_args(c, 1, 0, x, c->v_r, sc), s));
+    HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.x), vec(c, c->w.r), sc), s));
     c->ev_used = 0;
-    launch_schwarz_timed(c, schwarz_args(c, 1, c->v_r, sc));
-    HIPCHK(launch_pupdate(pupdate_args(c, 1, 0, c->v_p, sc), s));
-    int j = 1;
-    int chunk = c->prev_iters > 0 ? std::max(1, c->prev_iters) : c->chunk;
-    bool done = false;
-    while (!done) {
-        for (int k = 0; k < chunk && j <= maxit; ++k, ++j) {
-            SpmvArgs q{};
-            q.mode = SPMV_PQ;
-            q.x = c->v_p;
-            q.y = c->v_q;
-            q.part = c->d_spart;
-            q.sc = sc;
-            HIPCHK(launch_spmv(c->dA, q, s));
-            HIPCHK(launch_update(update_args(c, 0, j, x, c->v_r, sc), s));
-            launch_schwarz_timed(c, schwarz_args(c, 2, c->v_r, sc));
-            HIPCHK(launch_pupdate(pupdate_args(c, 2, j, c->v_p, sc), s));
+    launch_schwarz_timed(c, schwarz_args(c, 1, vec(c, c->w.r), sc));
+    HIPCHK(launch_pupdate(pupdate_args(c, 1, vec(c, c->w.p), sc), s));
+    PcgRun &R = c->run;
+    R = PcgRun();
+    R.x = x;
+    R.b = step_mode ? vec(c, c->w.b) : b;
+    R.step = step_mode;
+    R.maxit = maxit;
+    R.j = 1;
+    R.next = c->prev_iters > 0 ? c->prev_iters : c->chunk;
+    R.active = true;
+}
+
+// Launches the next chunk of iterations and the copy of the device scalars.
+void pcg_launch(pdg_ctx *c) {
+    PcgRun &R = c->run;
+    const int count = std::min(R.next, R.maxit - R.j + 1);
+    if (count > 0) {
+        if (c->use_graph && !c->timing) {
+            ensure_graph(c);
+            const int reps = (count + c->gexec_chunk - 1) / c->gexec_chunk;
+            for (int k = 0; k < reps; ++k) HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+            R.j += reps * c->gexec_chunk;
+        } else {
+            for (int k = 0; k < count; ++k) launch_iteration(c, true);
+            R.j += count;
         }
-        HIPCHK(hipMemcpyAsync(c->sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        done = c->sc_host->done || j > maxit;
-        chunk = c->chunk;
     }
-    const DevScalars h = *c->sc_host;
-    // Schwarz launches that did work: init + iterations 1..iters (convergence is
-    // detected after the Schwarz kernel of the converged iteration)
-    harvest_timing(c, (size_t)h.iters + 1);
-    if (h.status == ST_ZERO_RHS) HIPCHK(launch_zero(x, c->mesh.n_elem * c->mesh.nd, s));
-    pdg_solve_info out{};
-    out.iters = h.iters;
-    out.bnorm = std::sqrt(h.bb);
-    out.relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-    out.true_relres = -1.0;
-    if (c->true_resid && h.bb > 0) {
+    R.next = c->chunk;
+    HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, c->n_sys * sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+}
+
+// Waits for the last pcg_launch; true when every system has stopped.
+bool pcg_poll(pdg_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    PcgRun &R = c->run;
+    bool all = true;
+    for (int b = 0; b < c->n_sys && all; ++b) all = c->sc_host[b].done != 0;
+    return all || R.j > R.maxit;
+}
+
+// Writes the iterate to the caller's x, computes the optional true residuals
+// and the per-system results; returns the first non-OK system status.
+pdg_status pcg_end(pdg_ctx *c, pdg_solve_info *info, int *bad_sys) {
+    PcgRun &R = c->run;
+    R.active = false;
+    hipStream_t s = c->stream;
+    const int n_sys = c->n_sys;
+    c->last.assign(c->sc_host, c->sc_host + n_sys);
+    int max_it = 0;
+    for (const DevScalars &h : c->last) max_it = std::max(max_it, h.iters);
+    // Schwarz launches that did work: init + iterations 1..max iters
+    harvest_timing(c, (size_t)max_it + 1);
+    HIPCHK(launch_finish(vec(c, c->w.x), R.x, wptr<int32_t>(c, c->w.elsys), c->mesh.nd, c->mesh.n_elem, c->sc, s));
+    c->last_true.assign(n_sys, -1.0);
+    if (!c->true_resid) HIPCHK(hipStreamSynchronize(s));  // outputs complete on return
+    if (c->true_resid) {
         SpmvArgs t{};
         t.mode = SPMV_RESID;
-        t.x = x;
-        t.b = step_mode ? c->v_b : b;
-        t.y = c->v_t;
-        t.part = c->d_spart;
-        t.sc = sc;
+        t.x = R.x;
+        t.b = R.b;
+        t.y = vec(c, c->w.t);
+        t.part = vec(c, c->w.part);
+        t.sc = c->sc;
         HIPCHK(launch_spmv(c->dA, t, s));
-        HIPCHK(launch_sum_partials(c->d_spart, (int)c->n_groups, 1, &sc->tr, s));
-        HIPCHK(hipMemcpyAsync(c->sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        HIPCHK(launch_sum_partials(vec(c, c->w.part), wptr<int32_t>(c, c->w.rspmv), n_sys, 1, c->sc, s));
+        HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, n_sys * sizeof(DevScalars), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        out.true_relres = std::sqrt(c->sc_host->tr / h.bb);
+        for (int b = 0; b < n_sys; ++b)
+            if (c->last[b].bb > 0) c->last_true[b] = std::sqrt(c->sc_host[b].tr / c->last[b].bb);
     }
+    pdg_solve_info out{};
+    double bb = 0.0;
+    out.true_relres = c->true_resid ? 0.0 : -1.0;
+    pdg_status st = PDG_OK;
+    if (bad_sys) *bad_sys = -1;
+    for (int b = 0; b < n_sys; ++b) {
+        const DevScalars &h = c->last[b];
+        out.iters = std::max(out.iters, h.iters);
+        bb += h.bb;
+        out.relres = std::max(out.relres, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0);
+        if (c->true_resid) out.true_relres = std::max(out.true_relres, c->last_true[b]);
+        const pdg_status sb = map_status(h.status == ST_RUN ? ST_NOCONV : h.status);
+        if (sb != PDG_OK && st == PDG_OK) {
+            st = sb;
+            if (bad_sys) *bad_sys = b;
+        }
+    }
+    out.bnorm = std::sqrt(bb);
     if (info) *info = out;
-    c->prev_iters = h.iters;
-    int st = h.status;
-    if (st == ST_RUN) st = ST_NOCONV;
-    return map_status(st);
+    c->prev_iters = max_it;
+    return st;
+}
+
+pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u_prev, const double *f_ext,
+                   double tol, int maxit, pdg_solve_info *info, int *bad_sys) {
+    pcg_begin(c, x, b, step_mode, u_prev, f_ext, tol, maxit);
+    do pcg_launch(c);
+    while (!pcg_poll(c));
+    return pcg_end(c, info, bad_sys);
+}
+
+void launch_ionic_step(pdg_ctx *c, const double *u, const double *u_prev, double *ions, double *I) {
+    HIPCHK(launch_status_reset(c->sc, c->n_sys, 0.0, 0, 1, c->stream));
+    IonicArgs a{};
+    a.dim = c->mesh.dim;
+    a.p = c->mesh.p;
+    a.nd = c->mesh.nd;
+    a.n_elem = c->mesh.n_elem;
+    a.qp_ptr = wptr<int64_t>(c, c->w.qpptr);
+    a.qp_xi = vec(c, c->w.qpxi);
+    a.qp_w = vec(c, c->w.qpw);
+    a.norm = vec(c, c->w.norm);
+    a.minv = vec(c, c->w.minv);
+    a.u = u;
+    a.u_prev = u_prev;
+    a.y = ions;
+    a.I = I;
+    a.prm = vec(c, c->w.prm);
+    a.dt = c->dt;
+    a.bad = &c->sc[0].ionic_bad;
+    HIPCHK(launch_ionic(a, c->stream));
+}
+
+std::string pcg_message(pdg_status st, int bad_sys, int n_sys) {
+    std::string m = std::string("PCG: ") + pdg_status_string(st);
+    if (n_sys > 1 && bad_sys >= 0) m += " (system " + std::to_string(bad_sys) + ")";
+    return m;
 }
 
 }  // namespace
@@ -518,9 +810,6 @@ pdg_status pdg_create(pdg_ctx **out, int32_t hip_device, void *hip_stream) {
             HIPCHK(hipGetDeviceCount(&n));
             if (hip_device >= n) throw Error(PDG_EINVAL, "no such HIP device");
             HIPCHK(hipSetDevice(hip_device));
-            void *h = nullptr;
-            HIPCHK(hipHostMalloc(&h, sizeof(DevScalars), hipHostMallocDefault));
-            c->sc_host = reinterpret_cast<DevScalars *>(h);
         }
     });
     if (st != PDG_OK) {
@@ -534,7 +823,8 @@ pdg_status pdg_create(pdg_ctx **out, int32_t hip_device, void *hip_stream) {
 void pdg_destroy(pdg_ctx *c) {
     if (!c) return;
     if (c->device >= 0) {
-        if (c->stream || c->state >= S_BOUND) (void)hipStreamSynchronize(c->stream);
+        if (c->state >= S_BOUND) (void)hipStreamSynchronize(c->stream);
+        drop_graph(c);
         for (auto &e : c->ev_pool) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -549,8 +839,34 @@ const char *pdg_last_error(const pdg_ctx *c) { return c ? c->err.c_str() : "ctx 
 pdg_status pdg_set_mesh(pdg_ctx *c, const pdg_mesh *mesh, int32_t p) {
     return guard(c, [&] {
         require(c, S_CREATED, "pdg_set_mesh");
+        if (c->state >= S_MESH) throw Error(PDG_ESTATE, "pdg_set_mesh: mesh already set");
         build_mesh(c->mesh, mesh, p);
+        c->n_sys = 1;
+        c->sys_elem_ptr = {0, c->mesh.n_elem};
+        c->elem_sys.assign(c->mesh.n_elem, 0);
         c->state = S_MESH;
+    });
+}
+
+pdg_status pdg_set_systems(pdg_ctx *c, int32_t n_sys, const int64_t *elem_ptr) {
+    return guard(c, [&] {
+        require(c, S_MESH, "pdg_set_systems");
+        if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "pdg_set_systems: call before pdg_setup_preconditioner");
+        const int64_t n = c->mesh.n_elem;
+        if (n_sys < 1 || !elem_ptr) throw Error(PDG_EINVAL, "n_sys < 1 or elem_ptr is NULL");
+        if (elem_ptr[0] != 0 || elem_ptr[n_sys] != n) throw Error(PDG_EINVAL, "elem_ptr must run from 0 to n_elem");
+        for (int b = 0; b < n_sys; ++b)
+            if (elem_ptr[b + 1] <= elem_ptr[b]) throw Error(PDG_EINVAL, "empty system");
+        std::vector<int32_t> es(n);
+        for (int b = 0; b < n_sys; ++b)
+            for (int64_t e = elem_ptr[b]; e < elem_ptr[b + 1]; ++e) es[e] = b;
+        for (int64_t f = 0; f < c->mesh.n_facet; ++f) {
+            const int64_t a = c->mesh.facet_elem[2 * f], b = c->mesh.facet_elem[2 * f + 1];
+            if (b >= 0 && es[a] != es[b]) throw Error(PDG_EINVAL, "a facet joins two systems");
+        }
+        c->n_sys = n_sys;
+        c->sys_elem_ptr.assign(elem_ptr, elem_ptr + n_sys + 1);
+        c->elem_sys = std::move(es);
     });
 }
 
@@ -568,6 +884,7 @@ pdg_status pdg_get_sizes(const pdg_ctx *cc, int64_t *n_elem, int32_t *nd, int64_
 pdg_status pdg_assemble(pdg_ctx *c, double chi_m, double c_m, double dt, double eta0) {
     return guard(c, [&] {
         require(c, S_MESH, "pdg_assemble");
+        if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "pdg_assemble: preconditioner already set up");
         if (!(chi_m > 0) || !(c_m > 0) || !(dt > 0) || !(eta0 >= 0)) throw Error(PDG_EINVAL, "bad constants");
         c->chi = chi_m;
         c->cm = c_m;
@@ -579,7 +896,6 @@ pdg_status pdg_assemble(pdg_ctx *c, double chi_m, double c_m, double dt, double 
         c->Minv.assign(c->M.size(), 0.0);
         for (int64_t e = 0; e < c->mesh.n_elem; ++e)
             element_inverse(nd, &c->M[e * nd * nd], &c->Minv[e * nd * nd]);
-        build_group_ell(c);
         c->state = S_ASSEMBLED;
     });
 }
@@ -603,94 +919,30 @@ pdg_status pdg_set_ionic(pdg_ctx *c, const double *params, int32_t n_params) {
             if (!std::isfinite(params[k])) throw Error(PDG_EINVAL, "ionic parameter not finite");
         c->ionic.assign(params, params + n_params);
         c->has_ionic = true;
-        if (c->state >= S_BOUND)
-            HIPCHK(hipMemcpyAsync(c->d_prm, c->ionic.data(), kIonicParams * 8, hipMemcpyHostToDevice, c->stream));
-        if (c->state >= S_BOUND) HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->state >= S_BOUND) {
+            HIPCHK(hipMemcpyAsync(vec(c, c->w.prm), c->ionic.data(), kIonicParams * 8, hipMemcpyHostToDevice,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
     });
 }
 
 pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
     return guard(c, [&] {
         require(c, S_ASSEMBLED, "pdg_setup_preconditioner");
-        if (c->state >= S_BOUND) throw Error(PDG_ESTATE, "preconditioner already bound to a workspace");
+        if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "preconditioner already set up");
         if (d && d->coarse_q > 1) throw Error(PDG_EINVAL, "coarse_q must be 0 or 1");
-        setup_precond(c->mesh, c->K, c->M, d, c->pc, c->n_threads);
-        if (c->pc.q > 0 && c->pc.N0 > kMaxLocalDofs) throw Error(PDG_EINVAL, "coarse system exceeds 6144 dofs");
-        // update chunks: runs of at most 32 elements inside one coarse element
-        // (or over the element order without a coarse level)
-        constexpr int kChunk = 32;
-        c->grp_ptr.assign(1, 0);
-        c->grp_elems.clear();
-        c->cchunk_ptr.assign(1, 0);
-        if (c->pc.q > 0) {
-            for (int cc = 0; cc < c->pc.n_coarse; ++cc) {
-                const int a0 = c->pc.coarse_ptr[cc], a1 = c->pc.coarse_ptr[cc + 1];
-                for (int e = a0; e < a1; e += kChunk) {
-                    for (int k = e; k < std::min(a1, e + kChunk); ++k) c->grp_elems.push_back(c->pc.coarse_elems[k]);
-                    c->grp_ptr.push_back((int32_t)c->grp_elems.size());
-                }
-                c->cchunk_ptr.push_back((int32_t)c->grp_ptr.size() - 1);
-            }
-        } else {
-            const int64_t n = c->mesh.n_elem;
-            for (int64_t e = 0; e < n; e += kChunk) {
-                for (int64_t k = e; k < std::min<int64_t>(n, e + kChunk); ++k) c->grp_elems.push_back((int32_t)k);
-                c->grp_ptr.push_back((int32_t)c->grp_elems.size());
-            }
-        }
-        // Schwarz work items: the stored tiles (I, J <= I) of each packed tile
-        // row, split into runs of ~item_kb KiB
-        c->it_sys.clear(); c->it_row.clear(); c->it_j0.clear(); c->it_nj.clear(); c->it_rt.clear();
-        c->rt_item0.assign(1, 0);
-        c->rt_k.clear(); c->rt_nt.clear(); c->rt_cbase.clear();
-        c->max_nj = 1;
-        int64_t nloc_tiles = 0;
-        for (int sidx = 0; sidx < c->pc.n_sub; ++sidx) nloc_tiles += c->pc.sys[sidx].nt * (c->pc.sys[sidx].nt + 1) / 2;
-        for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx) {
-            const int64_t nt = c->pc.sys[sidx].nt;
-            const int prec = (int)sidx < c->pc.n_sub ? c->pc.local_prec : c->pc.coarse_prec;
-            const int64_t jc = std::max<int64_t>(1, ((int64_t)c->item_kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
-            const int64_t cbase = (int)sidx < c->pc.n_sub ? c->pc.sys[sidx].tile_off : nloc_tiles;
-            for (int64_t I = 0; I < nt; ++I) {
-                const int32_t rt = (int32_t)c->rt_item0.size() - 1;
-                const int64_t ntile = I + 1, nc = (ntile + jc - 1) / jc;
-                for (int64_t k = 0; k < nc; ++k) {
-                    const int64_t j0 = k * ntile / nc, j1 = (k + 1) * ntile / nc;
-                    c->it_sys.push_back((int32_t)sidx);
-                    c->it_row.push_back((int32_t)I);
-                    c->it_j0.push_back((int32_t)j0);
-                    c->it_nj.push_back((int32_t)(j1 - j0));
-                    c->it_rt.push_back(rt);
-                    c->max_nj = std::max<int>(c->max_nj, (int)(j1 - j0));
-                }
-                c->rt_item0.push_back((int32_t)c->it_sys.size());
-                c->rt_k.push_back((int32_t)I);
-                c->rt_nt.push_back((int32_t)nt);
-                c->rt_cbase.push_back(cbase);
-            }
-        }
-        // tile row (and row inside it) of every fine dof, for assembling z
-        {
-            const int nd = c->mesh.nd;
-            c->dof_rt.assign(c->mesh.n_elem * nd, 0);
-            int32_t rt0 = 0;
-            for (int sidx = 0; sidx < c->pc.n_sub; ++sidx) {
-                const int a0 = c->pc.sub_ptr[sidx], a1 = c->pc.sub_ptr[sidx + 1];
-                for (int le = 0; le < a1 - a0; ++le)
-                    for (int i = 0; i < nd; ++i) {
-                        const int pos = le * nd + i;
-                        c->dof_rt[(int64_t)c->pc.sub_elems[a0 + le] * nd + i] = (rt0 + pos / kTile) * kTile + pos % kTile;
-                    }
-                rt0 += (int32_t)c->pc.sys[sidx].nt;
-            }
-            c->coarse_rt0 = c->pc.q > 0 ? rt0 : -1;
-        }
-        c->max_sys_n = 0;
-        for (auto &S : c->pc.sys) c->max_sys_n = std::max<int>(c->max_sys_n, (int)S.n);
+        setup_precond(c->mesh, c->K, c->M, d, c->elem_sys, c->n_sys, c->pc, c->n_threads);
+        build_group_ell(c);
+        plan_chunks(c);
+        plan_items(c, c->item_kb, false);
+        c->items_reserved = std::max<int64_t>((int64_t)c->it_sys.size(), plan_items(c, std::min(c->item_kb, 64), true));
+        c->r_owner.assign(c->n_sys, 0);
+        for (int b = 0; b < c->n_sys; ++b) c->r_owner[b] = (int32_t)(c->sys_elem_ptr[b] * c->mesh.nd / 256);
         // algorithmic bytes of one Schwarz apply: stored tiles + input gathers + outputs
         int64_t lt = 0, ctl = 0;
-        for (int s = 0; s < c->pc.n_sub; ++s) lt += c->pc.sys[s].nt * (c->pc.sys[s].nt + 1) / 2;
-        if (c->pc.q > 0) ctl = c->pc.sys[c->pc.n_sub].nt * (c->pc.sys[c->pc.n_sub].nt + 1) / 2;
+        for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx)
+            ((int)sidx < c->pc.n_sub ? lt : ctl) += c->pc.sys[sidx].nt * (c->pc.sys[sidx].nt + 1) / 2;
         const int64_t N = c->mesh.n_elem * c->mesh.nd;
         c->schwarz_bytes = lt * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.local_prec) +
                            ctl * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.coarse_prec) + 3 * N * 8 +
@@ -725,9 +977,25 @@ pdg_status pdg_get_coarse(const pdg_ctx *cc, double *P, double *K0) {
     pdg_ctx *c = const_cast<pdg_ctx *>(cc);
     return guard(c, [&] {
         require(c, S_PRECOND, "pdg_get_coarse");
-        if (c->pc.q == 0) throw Error(PDG_ESTATE, "no coarse level");
-        if (P) std::copy(c->pc.P.begin(), c->pc.P.end(), P);
-        if (K0) std::copy(c->pc.K0.begin(), c->pc.K0.end(), K0);
+        const Precond &pc = c->pc;
+        if (pc.q == 0) throw Error(PDG_ESTATE, "no coarse level");
+        if (P) std::copy(pc.P.begin(), pc.P.end(), P);
+        if (K0) {
+            // block diagonal over the systems, in the caller's coarse labels
+            const int nq = pc.nq0;
+            const int64_t N0 = pc.N0;
+            std::fill(K0, K0 + N0 * N0, 0.0);
+            for (int b = 0; b < c->n_sys; ++b) {
+                const int c0 = pc.csys_ce0[b];
+                const int64_t n0 = (int64_t)(pc.csys_ce0[b + 1] - c0) * nq;
+                for (int64_t i = 0; i < n0; ++i)
+                    for (int64_t j = 0; j < n0; ++j) {
+                        const int64_t gi = (int64_t)pc.coarse_orig[c0 + i / nq] * nq + i % nq;
+                        const int64_t gj = (int64_t)pc.coarse_orig[c0 + j / nq] * nq + j % nq;
+                        K0[gi * N0 + gj] = pc.K0blk[b][i * n0 + j];
+                    }
+            }
+        }
     });
 }
 
@@ -749,45 +1017,60 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) throw Error(PDG_EINVAL, "workspace must be 256-byte aligned");
         if (bytes < c->lay.total) throw Error(PDG_ENOMEM, "workspace too small");
         HIPCHK(hipSetDevice(c->device));
+        if (!c->sc_host) {
+            void *h = nullptr;
+            HIPCHK(hipHostMalloc(&h, c->n_sys * sizeof(DevScalars), hipHostMallocDefault));
+            c->sc_host = reinterpret_cast<DevScalars *>(h);
+            std::memset(c->sc_host, 0, c->n_sys * sizeof(DevScalars));
+        }
         c->ws = reinterpret_cast<char *>(dev_ptr);
         c->ws_bytes = bytes;
         const Mesh &m = c->mesh;
         const Precond &pc = c->pc;
-        const int64_t n = m.n_elem;
+        const Ws &w = c->w;
         const int nd = m.nd;
         // matrix
-        upload(c, W_GROWS, c->grp_rows);
-        upload(c, W_GSLOT, c->grp_slot_off);
-        upload(c, W_GCOL, c->grp_col);
-        upload(c, W_GVAL, c->grp_val);
-        upload(c, W_MASS, c->M);
-        upload(c, W_MINV, c->Minv);
-        upload(c, W_QPPTR, m.qp_ptr);
-        upload(c, W_QPXI, m.qp_xi);
-        upload(c, W_QPW, m.qp_w);
-        upload(c, W_NORM, m.norm);
+        upload(c, w.grows, c->grp_rows);
+        upload(c, w.gslot, c->grp_slot_off);
+        upload(c, w.gcol, c->grp_col);
+        upload(c, w.gval, c->grp_val);
+        upload(c, w.gsys, c->grp_sys);
+        upload(c, w.mass, c->M);
+        upload(c, w.minv, c->Minv);
+        upload(c, w.qpptr, m.qp_ptr);
+        upload(c, w.qpxi, m.qp_xi);
+        upload(c, w.qpw, m.qp_w);
+        upload(c, w.norm, m.norm);
         std::vector<double> prm(kIonicParams, 0.0);
         if (c->has_ionic) prm = c->ionic;
-        upload(c, W_PRM, prm);
-        upload(c, W_SUBPTR, pc.sub_ptr);
-        upload(c, W_SUBEL, pc.sub_elems);
-        upload(c, W_ITSYS, c->it_sys);
-        upload(c, W_ITROW, c->it_row);
-        upload(c, W_ITJ0, c->it_j0);
-        upload(c, W_ITNJ, c->it_nj);
-        upload(c, W_ITRT, c->it_rt);
-        upload(c, W_RTIT0, c->rt_item0);
+        upload(c, w.prm, prm);
+        upload(c, w.subptr, pc.sub_ptr);
+        upload(c, w.subel, pc.sub_elems);
+        upload(c, w.dofrt, c->dof_rt);
+        upload(c, w.rtk, c->rt_k);
+        upload(c, w.rtnt, c->rt_nt);
+        upload(c, w.rtcb, c->rt_cbase);
+        upload(c, w.crt0, c->coarse_rt0);
+        upload(c, w.csys0, pc.q > 0 ? pc.csys_ce0 : std::vector<int32_t>(c->n_sys + 1, 0));
+        upload(c, w.rspmv, c->r_spmv);
+        upload(c, w.rupd, c->r_upd);
+        upload(c, w.rowner, c->r_owner);
+        upload(c, w.elsys, c->elem_sys);
         std::vector<int32_t> sys_n, sys_nt;
-        std::vector<int64_t> sys_toff;
-        for (size_t s = 0; s < pc.sys.size(); ++s) {
-            sys_n.push_back((int32_t)pc.sys[s].n);
-            sys_nt.push_back((int32_t)pc.sys[s].nt);
-            // local systems index the local store; the coarse system its own store
-            sys_toff.push_back((int)s < pc.n_sub ? pc.sys[s].tile_off : 0);
+        std::vector<int64_t> sys_toff, sys_cb;
+        int64_t nloc_tiles = 0;
+        for (int sidx = 0; sidx < pc.n_sub; ++sidx) nloc_tiles += pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2;
+        for (size_t sidx = 0; sidx < pc.sys.size(); ++sidx) {
+            sys_n.push_back((int32_t)pc.sys[sidx].n);
+            sys_nt.push_back((int32_t)pc.sys[sidx].nt);
+            // local systems index the local store, coarse systems the coarse store
+            sys_toff.push_back((int)sidx < pc.n_sub ? pc.sys[sidx].tile_off : pc.sys[sidx].tile_off - nloc_tiles);
+            sys_cb.push_back(pc.sys[sidx].tile_off);
         }
-        upload(c, W_SYSN, sys_n);
-        upload(c, W_SYSNT, sys_nt);
-        upload(c, W_SYSTOFF, sys_toff);
+        upload(c, w.sysn, sys_n);
+        upload(c, w.sysnt, sys_nt);
+        upload(c, w.systoff, sys_toff);
+        upload(c, w.syscb, sys_cb);
         // subdomains whose elements form one contiguous run gather r directly
         std::vector<int64_t> sys_dof0(pc.sys.size(), -1);
         for (int sidx = 0; sidx < pc.n_sub; ++sidx) {
@@ -796,22 +1079,9 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
             for (int k = a0 + 1; k < a1 && contiguous; ++k) contiguous = pc.sub_elems[k] == pc.sub_elems[k - 1] + 1;
             if (contiguous) sys_dof0[sidx] = (int64_t)pc.sub_elems[a0] * nd;
         }
-        upload(c, W_SYSDOF0, sys_dof0);
-        {
-            int64_t nloc_tiles = 0;
-            for (int sidx = 0; sidx < pc.n_sub; ++sidx) nloc_tiles += pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2;
-            std::vector<int64_t> sys_cbase(pc.sys.size());
-            for (size_t sidx = 0; sidx < pc.sys.size(); ++sidx)
-                sys_cbase[sidx] = (int)sidx < pc.n_sub ? pc.sys[sidx].tile_off : nloc_tiles;
-            upload(c, W_SYSCB, sys_cbase);
-        }
-        upload(c, W_RTK, c->rt_k);
-        upload(c, W_RTNT, c->rt_nt);
-        upload(c, W_RTCB, c->rt_cbase);
+        upload(c, w.sysdof0, sys_dof0);
         // tiles, converted to the storage precision
-        int64_t local_tiles = 0;
-        for (int s = 0; s < pc.n_sub; ++s) local_tiles += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
-        const int64_t nloc = local_tiles * kTile * kTile;
+        const int64_t nloc = nloc_tiles * kTile * kTile;
         const int64_t ncoa = (int64_t)pc.inv64.size() - nloc;
         std::vector<float> f32;
         std::vector<uint16_t> b16;
@@ -831,74 +1101,32 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
                 HIPCHK(hipStreamSynchronize(c->stream));
             }
         };
-        put_tiles(W_TLOC, pc.inv64.data(), nloc, pc.local_prec);
-        put_tiles(W_TCOA, pc.inv64.data() + nloc, ncoa, pc.coarse_prec);
-        upload(c, W_P, pc.P);
-        upload(c, W_ECOA, pc.elem_coarse);
-        upload(c, W_GRPPTR, c->grp_ptr);
-        upload(c, W_GRPEL, c->grp_elems);
-        upload(c, W_CCHUNK, c->cchunk_ptr);
-        upload(c, W_DOFRT, c->dof_rt);
-        HIPCHK(hipMemsetAsync(c->ws + c->lay.items[W_SC].off, 0, 2 * 256, c->stream));
-        for (int k = W_R; k <= W_Z0; ++k)
+        put_tiles(w.tloc, pc.inv64.data(), nloc, pc.local_prec);
+        put_tiles(w.tcoa, pc.inv64.data() + nloc, ncoa, pc.coarse_prec);
+        upload(c, w.P, pc.P);
+        upload(c, w.ecoa, pc.elem_coarse);
+        upload(c, w.grpptr, c->grp_ptr);
+        upload(c, w.grpel, c->grp_elems);
+        upload(c, w.upsys, c->upd_sys);
+        upload(c, w.cchunk, c->cchunk_ptr);
+        for (int k : {w.sc, w.sca})
             HIPCHK(hipMemsetAsync(c->ws + c->lay.items[k].off, 0, c->lay.items[k].bytes, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        // device pointers
+        for (int k : {w.x, w.r, w.z, w.p, w.q, w.I, w.t, w.b})
+            HIPCHK(hipMemsetAsync(c->ws + c->lay.items[k].off, 0, c->lay.items[k].bytes, c->stream));
+        upload_items(c);  // synchronises
         c->dA.nd = nd;
         c->dA.G = c->G;
-        c->dA.n_rows = n;
+        c->dA.wpg = c->spmv_wpg;
+        c->dA.n_rows = m.n_elem;
         c->dA.n_groups = c->n_groups;
-        c->dA.grp_rows = wptr<int32_t>(c, W_GROWS);
-        c->dA.grp_slot_off = wptr<int64_t>(c, W_GSLOT);
-        c->dA.grp_col = wptr<int32_t>(c, W_GCOL);
-        c->dA.grp_val = wptr<double>(c, W_GVAL);
-        c->dA.mass = wptr<double>(c, W_MASS);
-        c->d_minv = wptr<double>(c, W_MINV);
-        c->d_qp_ptr = wptr<int64_t>(c, W_QPPTR);
-        c->d_qp_xi = wptr<double>(c, W_QPXI);
-        c->d_qp_w = wptr<double>(c, W_QPW);
-        c->d_norm = wptr<double>(c, W_NORM);
-        c->d_prm = wptr<double>(c, W_PRM);
-        c->d_sub_ptr = wptr<int32_t>(c, W_SUBPTR);
-        c->d_sub_elems = wptr<int32_t>(c, W_SUBEL);
-        c->d_it_sys = wptr<int32_t>(c, W_ITSYS);
-        c->d_it_row = wptr<int32_t>(c, W_ITROW);
-        c->d_it_j0 = wptr<int32_t>(c, W_ITJ0);
-        c->d_it_nj = wptr<int32_t>(c, W_ITNJ);
-        c->d_it_rt = wptr<int32_t>(c, W_ITRT);
-        c->d_rt_item0 = wptr<int32_t>(c, W_RTIT0);
-        c->d_dof_rt = wptr<int32_t>(c, W_DOFRT);
-        c->d_itemdot = wptr<double>(c, W_ITDOT);
-        c->d_spart = wptr<double>(c, W_PART);
-        c->d_rrpart = wptr<double>(c, W_RRPART);
-        c->d_part = wptr<double>(c, W_SPART);
-        c->d_cchunk_ptr = wptr<int32_t>(c, W_CCHUNK);
-        c->d_sys_n = wptr<int32_t>(c, W_SYSN);
-        c->d_sys_nt = wptr<int32_t>(c, W_SYSNT);
-        c->d_sys_toff = wptr<int64_t>(c, W_SYSTOFF);
-        c->d_sys_dof0 = wptr<int64_t>(c, W_SYSDOF0);
-        c->d_sys_cbase = wptr<int64_t>(c, W_SYSCB);
-        c->d_rt_k = wptr<int32_t>(c, W_RTK);
-        c->d_rt_nt = wptr<int32_t>(c, W_RTNT);
-        c->d_rt_cbase = wptr<int64_t>(c, W_RTCB);
-        c->d_colpart = wptr<double>(c, W_COLP);
-        c->d_tiles_local = wptr<void>(c, W_TLOC);
-        c->d_tiles_coarse = wptr<void>(c, W_TCOA);
-        c->d_P = pc.q > 0 ? wptr<double>(c, W_P) : nullptr;
-        c->d_elem_coarse = pc.q > 0 ? wptr<int32_t>(c, W_ECOA) : nullptr;
-        c->d_grp_ptr = wptr<int32_t>(c, W_GRPPTR);
-        c->d_grp_elems = wptr<int32_t>(c, W_GRPEL);
-        c->v_r = wptr<double>(c, W_R);
-        c->v_z = wptr<double>(c, W_Z);
-        c->v_p = wptr<double>(c, W_PV);
-        c->v_q = wptr<double>(c, W_Q);
-        c->v_I = wptr<double>(c, W_I);
-        c->v_t = wptr<double>(c, W_T);
-        c->v_b = wptr<double>(c, W_B);
-        c->d_r0part = wptr<double>(c, W_R0P);
-        c->v_z0 = wptr<double>(c, W_Z0);
-        c->sc = wptr<DevScalars>(c, W_SC);
-        c->sc_apply = wptr<DevScalars>(c, W_SCA);
+        c->dA.grp_rows = wptr<int32_t>(c, w.grows);
+        c->dA.grp_slot_off = wptr<int64_t>(c, w.gslot);
+        c->dA.grp_col = wptr<int32_t>(c, w.gcol);
+        c->dA.grp_val = wptr<double>(c, w.gval);
+        c->dA.mass = wptr<double>(c, w.mass);
+        c->dA.grp_sys = wptr<int32_t>(c, w.gsys);
+        c->sc = wptr<DevScalars>(c, w.sc);
+        c->sc_apply = wptr<DevScalars>(c, w.sca);
         c->state = S_BOUND;
     });
 }
@@ -906,6 +1134,7 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
 pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
     return guard(c, [&] {
         require(c, S_CREATED, "pdg_set_option");
+        if (c->run.active) throw Error(PDG_ESTATE, "pdg_set_option: a solve is in progress");
         switch (option) {
         case PDG_OPT_TRUE_RESIDUAL: c->true_resid = value != 0; break;
         case PDG_OPT_CHUNK:
@@ -917,6 +1146,17 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             if (value < 32 || value > 8192) throw Error(PDG_EINVAL, "item size must be in 32..8192 KiB");
             if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "set the item size before pdg_setup_preconditioner");
             c->item_kb = (int)value;
+            break;
+        case PDG_OPT_GRAPH:
+            if (value != 0 && c->stream == nullptr)
+                throw Error(PDG_EINVAL, "graph replay needs a non-default stream (capture is not possible on it)");
+            c->use_graph = value != 0;
+            break;
+        case PDG_OPT_SPMV_WAVES:
+            if (value != 1 && value != 2 && value != 4 && value != 8) throw Error(PDG_EINVAL, "SpMV waves must be 1, 2, 4 or 8");
+            c->spmv_wpg = (int)value;
+            c->dA.wpg = (int)value;
+            drop_graph(c);
             break;
         default: throw Error(PDG_EINVAL, "unknown option");
         }
@@ -939,7 +1179,7 @@ pdg_status pdg_project_p0(pdg_ctx *c, const double *vals, int32_t ncomp, double 
     return guard(c, [&] {
         require_gpu(c);
         if (!vals || !coeff || ncomp < 1) throw Error(PDG_EINVAL, "bad arguments");
-        HIPCHK(launch_project_p0(vals, ncomp, c->mesh.n_elem, c->mesh.nd, c->d_norm, coeff, c->stream));
+        HIPCHK(launch_project_p0(vals, ncomp, c->mesh.n_elem, c->mesh.nd, vec(c, c->w.norm), coeff, c->stream));
     });
 }
 
@@ -960,12 +1200,12 @@ pdg_status pdg_precond_apply(pdg_ctx *c, const double *r, double *z) {
         require_gpu(c);
         if (!r || !z) throw Error(PDG_EINVAL, "NULL vector");
         DevScalars *sc = c->sc_apply;
-        HIPCHK(launch_status_reset(sc, -1.0, 0, 0, c->stream));
+        HIPCHK(launch_status_reset(sc, c->n_sys, -1.0, 0, 0, c->stream));
         // restriction only (init mode: x and r untouched)
-        HIPCHK(launch_update(update_args(c, 1, 0, c->v_t, const_cast<double *>(r), sc), c->stream));
+        HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.t), const_cast<double *>(r), sc), c->stream));
         c->ev_used = 0;
         launch_schwarz_timed(c, schwarz_args(c, 0, r, sc));
-        HIPCHK(launch_pupdate(pupdate_args(c, 0, 0, z, sc), c->stream));
+        HIPCHK(launch_pupdate(pupdate_args(c, 0, z, sc), c->stream));
         if (c->timing) {
             HIPCHK(hipStreamSynchronize(c->stream));
             harvest_timing(c, 1);
@@ -978,25 +1218,7 @@ pdg_status pdg_ionic(pdg_ctx *c, const double *u, const double *u_prev, double *
         require_gpu(c);
         if (!c->has_ionic) throw Error(PDG_ESTATE, "pdg_set_ionic not called");
         if (!u || !u_prev || !ions || !I) throw Error(PDG_EINVAL, "NULL vector");
-        HIPCHK(launch_status_reset(c->sc, 0.0, 0, 1, c->stream));
-        IonicArgs a{};
-        a.dim = c->mesh.dim;
-        a.p = c->mesh.p;
-        a.nd = c->mesh.nd;
-        a.n_elem = c->mesh.n_elem;
-        a.qp_ptr = c->d_qp_ptr;
-        a.qp_xi = c->d_qp_xi;
-        a.qp_w = c->d_qp_w;
-        a.norm = c->d_norm;
-        a.minv = c->d_minv;
-        a.u = u;
-        a.u_prev = u_prev;
-        a.y = ions;
-        a.I = I;
-        a.prm = c->d_prm;
-        a.dt = c->dt;
-        a.sc = c->sc;
-        HIPCHK(launch_ionic(a, c->stream));
+        launch_ionic_step(c, u, u_prev, ions, I);
         HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         if (c->sc_host->ionic_bad) throw Error(PDG_ENONFINITE, "ionic: non-positive concentration before a logarithm");
@@ -1020,14 +1242,13 @@ pdg_status pdg_rhs(pdg_ctx *c, const double *u, const double *I, const double *f
 }
 
 pdg_status pdg_solve(pdg_ctx *c, const double *rhs, double *x, double tol, int32_t maxit, pdg_solve_info *info) {
-    pdg_status st = PDG_OK;
-    pdg_status g = guard(c, [&] {
+    return guard(c, [&] {
         require_gpu(c);
         if (!rhs || !x) throw Error(PDG_EINVAL, "NULL vector");
-        st = run_pcg(c, x, rhs, false, nullptr, nullptr, tol, maxit, info);
-        if (st != PDG_OK) throw Error(st, std::string("PCG: ") + pdg_status_string(st));
+        int bad = -1;
+        const pdg_status st = run_pcg(c, x, rhs, false, nullptr, nullptr, tol, maxit, info, &bad);
+        if (st != PDG_OK) throw Error(st, pcg_message(st, bad, c->n_sys));
     });
-    return g;
 }
 
 pdg_status pdg_step(pdg_ctx *c, double *u, double *u_prev, double *ions, const double *f_ext, double tol,
@@ -1036,28 +1257,156 @@ pdg_status pdg_step(pdg_ctx *c, double *u, double *u_prev, double *ions, const d
         require_gpu(c);
         if (!c->has_ionic) throw Error(PDG_ESTATE, "pdg_set_ionic not called");
         if (!u || !u_prev || !ions) throw Error(PDG_EINVAL, "NULL vector");
-        HIPCHK(launch_status_reset(c->sc, 0.0, 0, 1, c->stream));
-        IonicArgs a{};
-        a.dim = c->mesh.dim;
-        a.p = c->mesh.p;
-        a.nd = c->mesh.nd;
-        a.n_elem = c->mesh.n_elem;
-        a.qp_ptr = c->d_qp_ptr;
-        a.qp_xi = c->d_qp_xi;
-        a.qp_w = c->d_qp_w;
-        a.norm = c->d_norm;
-        a.minv = c->d_minv;
-        a.u = u;
-        a.u_prev = u_prev;
-        a.y = ions;
-        a.I = c->v_I;
-        a.prm = c->d_prm;
-        a.dt = c->dt;
-        a.sc = c->sc;
-        HIPCHK(launch_ionic(a, c->stream));
-        pdg_status st = run_pcg(c, u, nullptr, true, u_prev, f_ext, tol, maxit, info);
-        if (c->sc_host->ionic_bad) throw Error(PDG_ENONFINITE, "ionic: non-positive concentration before a logarithm");
-        if (st != PDG_OK) throw Error(st, std::string("PCG: ") + pdg_status_string(st));
+        launch_ionic_step(c, u, u_prev, ions, vec(c, c->w.I));
+        int bad = -1;
+        const pdg_status st = run_pcg(c, u, nullptr, true, u_prev, f_ext, tol, maxit, info, &bad);
+        if (c->sc_host[0].ionic_bad) throw Error(PDG_ENONFINITE, "ionic: non-positive concentration before a logarithm");
+        if (st != PDG_OK) throw Error(st, pcg_message(st, bad, c->n_sys));
+    });
+}
+
+pdg_status pdg_step_batch(pdg_ctx *const *ctxs, int32_t n_ctx, double *const *u, double *const *u_prev,
+                          double *const *ions, const double *const *f_ext, double tol, int32_t maxit,
+                          pdg_solve_info *info) {
+    if (!ctxs || n_ctx < 1 || !ctxs[0]) return PDG_EINVAL;
+    pdg_ctx *c0 = ctxs[0];
+    pdg_status result = PDG_OK;
+    const pdg_status g = guard(c0, [&] {
+        if (!u || !u_prev || !ions) throw Error(PDG_EINVAL, "NULL pointer array");
+        for (int k = 0; k < n_ctx; ++k) {
+            pdg_ctx *c = ctxs[k];
+            require_gpu(c);
+            if (!c->has_ionic) throw Error(PDG_ESTATE, "pdg_set_ionic not called");
+            if (!u[k] || !u_prev[k] || !ions[k]) throw Error(PDG_EINVAL, "NULL vector");
+            for (int l = 0; l < k; ++l)
+                if (ctxs[l] == c) throw Error(PDG_EINVAL, "a context appears twice");
+        }
+        std::vector<char> live(n_ctx, 1);
+        for (int k = 0; k < n_ctx; ++k) {
+            pdg_ctx *c = ctxs[k];
+            launch_ionic_step(c, u[k], u_prev[k], ions[k], vec(c, c->w.I));
+            pcg_begin(c, u[k], nullptr, true, u_prev[k], f_ext ? f_ext[k] : nullptr, tol, maxit);
+        }
+        // chunks of all live contexts are queued before any poll waits
+        for (int n_live = n_ctx; n_live > 0;) {
+            for (int k = 0; k < n_ctx; ++k)
+                if (live[k]) pcg_launch(ctxs[k]);
+            for (int k = 0; k < n_ctx; ++k)
+                if (live[k] && pcg_poll(ctxs[k])) {
+                    live[k] = 0;
+                    --n_live;
+                }
+        }
+        std::string msg;
+        for (int k = 0; k < n_ctx; ++k) {
+            pdg_ctx *c = ctxs[k];
+            int bad = -1;
+            pdg_status st = pcg_end(c, info ? &info[k] : nullptr, &bad);
+            if (c->sc_host[0].ionic_bad && st == PDG_OK) st = PDG_ENONFINITE;
+            if (st != PDG_OK && result == PDG_OK) {
+                result = st;
+                msg = "context " + std::to_string(k) + ": " +
+                      (c->sc_host[0].ionic_bad ? std::string("ionic: non-positive concentration before a logarithm")
+                                               : pcg_message(st, bad, c->n_sys));
+            }
+        }
+        if (result != PDG_OK) throw Error(result, msg);
+    });
+    return g;
+}
+
+pdg_status pdg_get_system_info(const pdg_ctx *cc, int32_t sys, pdg_solve_info *info, int32_t *status) {
+    pdg_ctx *c = const_cast<pdg_ctx *>(cc);
+    return guard(c, [&] {
+        require_gpu(c);
+        if (sys < 0 || sys >= c->n_sys) throw Error(PDG_EINVAL, "system index out of range");
+        if (c->last.empty()) throw Error(PDG_ESTATE, "no solve yet");
+        const DevScalars &h = c->last[sys];
+        if (info) {
+            info->iters = h.iters;
+            info->bnorm = std::sqrt(h.bb);
+            info->relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+            info->true_relres = c->last_true[sys];
+        }
+        if (status) *status = map_status(h.status == ST_RUN ? ST_NOCONV : h.status);
+    });
+}
+
+pdg_status pdg_autotune(pdg_ctx *c, int32_t reps, pdg_tune_result *out) {
+    return guard(c, [&] {
+        require_gpu(c);
+        if (reps < 1 || reps > 1000) throw Error(PDG_EINVAL, "reps must be in 1..1000");
+        hipStream_t s = c->stream;
+        HIPCHK(hipStreamSynchronize(s));
+        drop_graph(c);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto time_ms = [&](auto &&body) {
+            body();  // warm-up
+            HIPCHK(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) body();
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms / reps;
+        };
+        pdg_tune_result res{};
+        try {
+            // Schwarz work-item size: the restriction shares are formed once,
+            // then only the Schwarz kernel is timed
+            DevScalars *sc = c->sc_apply;
+            double *r = vec(c, c->w.r);
+            HIPCHK(launch_status_reset(sc, c->n_sys, -1.0, 0, 0, s));
+            HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.t), r, sc), s));
+            const int cand[] = {64, 128, 256, 512, 1024};
+            int best_kb = c->item_kb;
+            double best = 1e300;
+            for (int kb : cand) {
+                if (plan_items(c, kb, true) > c->items_reserved) continue;
+                plan_items(c, kb, false);
+                if (schwarz_lds_bytes(store_kind(c->pc.local_prec), store_kind(c->pc.coarse_prec), c->max_nj) > 65536)
+                    continue;
+                upload_items(c);
+                const double ms = time_ms([&] { launch_schwarz_plain(c, schwarz_args(c, 0, r, sc)); });
+                if (ms < best) {
+                    best = ms;
+                    best_kb = kb;
+                }
+            }
+            plan_items(c, best_kb, false);
+            upload_items(c);
+            c->item_kb = best_kb;
+            res.item_kb = best_kb;
+            res.schwarz_us = best * 1e3;
+            // SpMV wavefronts per group
+            int best_w = c->spmv_wpg;
+            best = 1e300;
+            for (int wv : {1, 2, 4, 8}) {
+                c->dA.wpg = wv;
+                SpmvArgs a{};
+                a.mode = SPMV_PLAIN;
+                a.x = vec(c, c->w.p);
+                a.y = vec(c, c->w.t);
+                const double ms = time_ms([&] { HIPCHK(launch_spmv(c->dA, a, s)); });
+                if (ms < best) {
+                    best = ms;
+                    best_w = wv;
+                }
+            }
+            c->spmv_wpg = best_w;
+            c->dA.wpg = best_w;
+            res.spmv_waves = best_w;
+            res.spmv_us = best * 1e3;
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (out) *out = res;
     });
 }
 

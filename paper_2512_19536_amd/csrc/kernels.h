@@ -1,4 +1,12 @@
 // Kernel launch interface of libpdg (host side of kernels.hip).
+//
+// A context holds a batch of n_sys independent systems (one for a plain
+// solve).  Elements, dofs, SpMV groups, update chunks and Schwarz items are
+// ordered by system and never straddle two systems, so every per-workgroup
+// partial belongs to one system and each system runs its own PCG (own alpha,
+// beta and stopping test) inside the same launches.  No kernel takes an
+// iteration index: the counter lives in the device scalars, so a chunk of
+// iterations is a fixed sequence of launches that can be replayed as a graph.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -7,31 +15,43 @@
 
 namespace pdg {
 
-// Device-resident scalars of one PCG solve.  Written only by the last
-// workgroup of a reduction; read by every later kernel on the stream.
+// Device-resident scalars of one system's PCG.  Every field has one writer per
+// launch (the system's owner workgroup, thread 0); later launches read it.
 struct DevScalars {
-    double bb, rr, rz_unused, pq, alpha, beta, tol2;
+    double bb, rr, pq, alpha, beta, tol2;
     double tr;          // ||b - K x||^2 (true residual, optional)
-    int32_t done;       // 1 = stop launching work
-    int32_t status;     // 0 running/ok, 1 converged, 2 zero rhs, -5 noconv, -6 breakdown, -7 nonfinite
-    int32_t iters;
+    double rz[2];       // (r, z) of the search directions of even / odd index
+    int32_t done;       // 1 = this system stops
+    int32_t status;     // 0 running, 1 converged, 2 zero rhs, -5 noconv, -6 breakdown, -7 nonfinite
+    int32_t iters;      // completed iterations
+    int32_t jcur;       // iteration in progress (set by the update kernel, read by the p-update kernel)
     int32_t maxit;
-    int32_t ionic_bad;  // a concentration <= 0 met before a logarithm
-    int32_t pad[3];
-    double rz[2];       // (r, z) of iterations of even / odd index
+    int32_t ionic_bad;  // a concentration <= 0 met before a logarithm (system 0 holds the batch flag)
+    int32_t pad[2];
 };
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_ZERO_RHS = 2, ST_NOCONV = -5, ST_BREAKDOWN = -6, ST_NONFINITE = -7 };
 
-// Matrix in interleaved group-ELL form (see spmv kernel).
+// Per-system ranges of the partial-sum producers: system s owns [x[s], x[s+1]).
+struct SysRanges {
+    int n_sys;
+    const int32_t *spmv;    // SpMV workgroups (groups)
+    const int32_t *upd;     // update chunks
+    const int32_t *item;    // Schwarz items
+    const int32_t *owner;   // [n_sys] p-update workgroup holding the system's first dof
+};
+
+// Matrix in interleaved group-ELL form (see the SpMV kernel).
 struct DevMatrix {
     int nd, G;              // block size, block rows per group
+    int wpg;                // wavefronts per group (1, 2, 4 or 8)
     int64_t n_rows, n_groups;
     const int32_t *grp_rows;     // [n_groups*G] row ids (-1 = padding)
     const int64_t *grp_slot_off; // [n_groups+1] slot offsets
     const int32_t *grp_col;      // [slots*G]
     const double *grp_val;       // [slots*G*nd*nd]
     const double *mass;          // [n_rows][nd][nd]
+    const int32_t *grp_sys;      // [n_groups] system of each group
 };
 
 enum SpmvMode { SPMV_PLAIN = 0, SPMV_PQ = 1, SPMV_RESID = 2, SPMV_STEP = 3, SPMV_RHS = 4 };
@@ -44,45 +64,48 @@ struct SpmvArgs {
     const double *I;        // STEP/RHS: ion term
     const double *f;        // STEP/RHS: optional applied current (nullable)
     double *u_prev;         // STEP: receives a copy of x
+    double *xcopy;          // STEP/RESID: receives a copy of x (the PCG iterate), nullable
     double two_c, chi;      // STEP/RHS constants
-    double *part;           // [gridDim][2] per-workgroup sums (PQ: (p,q); RESID: ||b||^2, ||r||^2; STEP: ||b||^2)
-    DevScalars *sc;
+    double *part;           // [groups][2] per-workgroup sums (PQ: (p,q); RESID: ||b||^2, ||r||^2; STEP: ||b||^2)
+    DevScalars *sc;         // [n_sys]
 };
 
 struct UpdateArgs {
-    int init;               // 1: no x/r update, iteration 0
-    int iter;               // iteration index j (1-based) for the update
+    int init;               // 1: no x/r update (iteration 0)
     int nd, nq0;
-    const int32_t *grp_ptr, *grp_elems;  // update chunks: element ranges, each inside one coarse element
+    const int32_t *grp_ptr, *grp_elems;  // update chunks: element runs inside one coarse element
+    const int32_t *grp_sys;              // system of each chunk
     int n_grp;
     double *x, *r;
     const double *p, *q;
     const double *P;        // [n_elem][nd][nq0] or null
     double *r0part;         // [n_grp][nq0] per-chunk restriction, or null
-    const double *pqpart;   // [n_pq][2] SpMV partials ((p, q) in slot 0)
-    int n_pq;
+    const double *pqpart;   // SpMV partials ((p, q) in slot 0)
     double *rrpart;         // [n_grp] per-chunk ||r||^2
+    SysRanges rng;
     DevScalars *sc;
 };
 
 // Work item of the Schwarz kernel: stored tiles (I, J), J in [j0, j0 + nj),
-// of packed tile row I of system `sys` (all J <= I).  Each stored tile is
-// read once and used twice: as stored for z_I (accumulated over the item,
-// written as the item's row partial) and transposed for z_J, J < I (written as
-// the tile's column partial).  The consumer adds the partials in fixed order.
+// of packed tile row I of dense system `sys` (a subdomain, or the coarse
+// system of one batch system; all J <= I).  Each stored tile is read once and
+// used twice: as stored for z_I (accumulated over the item, written as the
+// item's row partial) and transposed for z_J, J < I (written as the tile's
+// column partial).  The consumer adds the partials in fixed order.
 struct SchwarzArgs {
     int mode;               // 0 apply only, 1/2 inside PCG (also writes the (r, z) shares)
     int nd, n_sub, nq0;
-    const int32_t *item_sys, *item_row, *item_j0, *item_nj;
+    const int32_t *item_sys, *item_row, *item_j0, *item_nj, *item_owner;
     double *part;                // [n_items][64] row partials
     double *colpart;             // [n_tiles_total][64] column partials (indexed by global tile index)
     double *itemdot;             // [n_items] shares of (r, z) + (r0, z0)
     const int32_t *sys_n, *sys_nt;
-    const int64_t *sys_toff;     // tile offset of each system inside its own store
-    const int64_t *sys_cbase;    // global tile index of each system's first tile (column partials)
+    const int64_t *sys_toff;     // tile offset of each dense system inside its own store
+    const int64_t *sys_cbase;    // global tile index of each dense system's first tile
     const int64_t *sys_dof0;     // first dof of a subdomain whose elements are one contiguous run, else -1
-    const void *tiles_local;     // tile store of the local systems (storage type per launch)
-    const void *tiles_coarse;    // tile store of the coarse system
+    const int32_t *csys_ce0;     // [n_sys+1] first coarse element of each batch system
+    const void *tiles_local;     // tile store of the local systems
+    const void *tiles_coarse;    // tile store of the coarse systems
     const int32_t *sub_ptr, *sub_elems;
     const int32_t *cchunk_ptr;   // [n_coarse+1] update chunks of each coarse element
     const double *r;        // fine residual
@@ -92,28 +115,27 @@ struct SchwarzArgs {
 
 // Assembles z = B r from the Schwarz partials (row partials of the items of
 // a tile row, column partials of the stored tiles below it, and P z0) and
-// updates the search direction; in PCG modes it also closes the iteration:
-// (r, z), beta, convergence on ||r||^2.
+// updates the search direction; in PCG modes it also closes each system's
+// iteration: (r, z), beta, convergence on ||r||^2.
 struct PupdateArgs {
     int mode;               // 0: out = z; 1: PCG init, p = z; 2: PCG, p = z + beta p
-    int iter;
     int nd, nq0;
     int64_t n_elem;
     const double *P;
-    const int32_t *elem_coarse;
+    const int32_t *elem_coarse;  // coarse element of each element (system-contiguous numbering)
+    const int32_t *elem_sys;     // batch system of each element
     const int32_t *dof_rt;       // [N] tile row * 64 + row inside the tile, of every fine dof
     const int32_t *rt_item0;     // [n_rt+1] first item of each tile row
-    const int32_t *rt_k, *rt_nt; // tile-row index inside its system, tile rows of the system
-    const int64_t *rt_cbase;     // global tile index of the system's first tile
-    int coarse_rt0;              // first tile row of the coarse system (or -1)
+    const int32_t *rt_k, *rt_nt; // tile-row index inside its dense system, tile rows of the system
+    const int64_t *rt_cbase;     // global tile index of the dense system's first tile
+    const int32_t *coarse_rt0;   // [n_sys] first tile row of each batch system's coarse system
+    const int32_t *csys_ce0;     // [n_sys+1] first coarse element of each batch system
     const double *part;          // Schwarz row partials
     const double *colpart;       // Schwarz column partials
     const double *itemdot;
-    int n_items;
     const double *rrpart;        // update partials
-    int n_rr;
     const double *bbpart;        // SpMV partials of the right-hand side (init only)
-    int n_bb;
+    SysRanges rng;
     double *p;                   // output
     DevScalars *sc;
 };
@@ -128,25 +150,28 @@ struct IonicArgs {
     double *I;
     const double *prm;      // 24 ionic parameters
     double dt;
-    DevScalars *sc;
+    int32_t *bad;           // set to 1 when a concentration <= 0 is met
 };
 
 enum LocalStorage { STORE_F64 = 0, STORE_F32 = 1, STORE_BF16 = 2 };
 
 hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s);
-int spmv_blocks(const DevMatrix &A);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t s);
-// Launches the Schwarz kernel over items [item0, item0 + n_items) with the
-// given storage type; the coarse items (if any) use coarse_store.
 hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store,
                           int max_nj, hipStream_t s);
+// LDS bytes the Schwarz kernel needs for items of up to max_nj tiles.
+size_t schwarz_lds_bytes(int local_store, int coarse_store, int max_nj);
 hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s);
 hipError_t launch_ionic(const IonicArgs &a, hipStream_t s);
 hipError_t launch_project_p0(const double *vals, int ncomp, int64_t n_elem, int nd, const double *norm,
                              double *coeff, hipStream_t s);
-hipError_t launch_zero(double *x, int64_t n, hipStream_t s);
-hipError_t launch_status_reset(DevScalars *sc, double tol2, int maxit, int reset_ionic, hipStream_t s);
-// Sums `n` partials (stride 2, slot `slot`) into *out with one workgroup.
-hipError_t launch_sum_partials(const double *part, int n, int slot, double *out, hipStream_t s);
+hipError_t launch_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit, int reset_ionic,
+                               hipStream_t s);
+// Sums the SpMV partials (stride 2, slot `slot`) of each system into sc[s].tr.
+hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_sys, int slot, DevScalars *sc,
+                               hipStream_t s);
+// out = x on every dof, except 0 on the dofs of systems that stopped with a zero right-hand side.
+hipError_t launch_finish(const double *x, double *out, const int32_t *elem_sys, int nd, int64_t n_elem,
+                         const DevScalars *sc, hipStream_t s);
 
 }  // namespace pdg

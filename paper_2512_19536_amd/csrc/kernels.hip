@@ -9,14 +9,16 @@
 //                       and z0 = K_0^{-1} r0, with their shares of (r, z)
 //   k_pupdate           z = B r assembled, beta = (r, z)' / (r, z), p = z + beta p,
 //                       convergence test on ||r||^2
-// No kernel synchronises workgroups with atomics or device-scope fences (on
-// gfx950 a device-scope release fence writes back the L2 and costs tens of ns
-// per workgroup).  Instead every kernel writes per-workgroup partial sums and
-// the next kernel, after the kernel boundary, adds them in a fixed order in
-// each of its workgroups.  All sums therefore have a fixed order and two runs
-// give bitwise-equal results.  Every kernel returns at once when the
-// device-side "done" flag is set, so iterations queued past convergence cost
-// a launch each and change nothing.
+// A launch serves a batch of independent systems: every workgroup belongs to
+// one system (the p-update kernel's dof blocks may touch several and handle
+// each in turn), reads that system's device scalars and returns at once when
+// the system has stopped.  No kernel synchronises workgroups with atomics or
+// device-scope fences (on gfx950 a device-scope release fence writes back the
+// L2 and costs tens of ns per workgroup).  Instead every kernel writes
+// per-workgroup partial sums and the next kernel, after the kernel boundary,
+// adds the partials of its system in a fixed order in each of its workgroups.
+// All sums therefore have a fixed order and two runs give bitwise-equal
+// results; a system gives the same bits alone or inside a batch.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -67,6 +69,19 @@ __device__ inline double block_sum_partials(const double *part, int n, int strid
 
 __device__ inline bool finite(double x) { return __builtin_isfinite(x); }
 
+// Thread 0's value of v in every thread of the block.  Used for flags that
+// another workgroup of the same launch may write, so that all wavefronts of a
+// block take the same branch around its barriers.
+template <int BS>
+__device__ inline int block_bcast(int v) {
+    __shared__ int s;
+    if (threadIdx.x == 0) s = v;
+    __syncthreads();
+    const int r = s;
+    __syncthreads();
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Block-sparse SpMV over element rows in interleaved group-ELL form.
 // G = 64 / ND element rows form a group; lane (r, i) = (lane / ND, lane % ND)
@@ -78,7 +93,7 @@ __device__ inline bool finite(double x) { return __builtin_isfinite(x); }
 template <int ND, int WPG>
 __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
-    if (a.mode == SPMV_PQ && a.sc->done) return;
+    if (a.mode == SPMV_PQ && a.sc[A.grp_sys[blockIdx.x]].done) return;
     __shared__ double s_acc[WPG][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t g = blockIdx.x;
@@ -123,6 +138,7 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
         case SPMV_RESID: {
             const double bv = a.b[idx], rv = bv - acc;
             a.y[idx] = rv;
+            if (a.xcopy) a.xcopy[idx] = a.x[idx];
             part[0] = bv * bv;
             part[1] = rv * rv;
             break;
@@ -141,6 +157,7 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
             } else {
                 a.y[idx] = bv - acc;  // r0 = b - K u  (x0 = u)
                 a.u_prev[idx] = ur[i];
+                if (a.xcopy) a.xcopy[idx] = ur[i];
                 part[0] = bv * bv;
             }
             break;
@@ -162,15 +179,20 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
 // of a coarse element in chunk order when it gathers r0.
 template <int ND, int NQ>
 __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
-    DevScalars *sc = a.sc;
-    if (sc->done) return;
+    const int c = blockIdx.x, b = a.grp_sys[c];
+    DevScalars *sc = a.sc + b;
+    // the owner chunk may set `done` during this launch
+    if (block_bcast<128>(threadIdx.x == 0 ? sc->done : 0)) return;
     double alpha = 0.0;
     if (!a.init) {
-        const double pq = block_sum_partials<128>(a.pqpart, a.n_pq, 2, 0);
-        alpha = sc->rz[(a.iter - 1) & 1] / pq;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int g0 = a.rng.spmv[b];
+        const double pq = block_sum_partials<128>(a.pqpart + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 0);
+        const int j = sc->iters + 1;
+        alpha = sc->rz[(j - 1) & 1] / pq;
+        if (c == a.rng.upd[b] && threadIdx.x == 0) {
             sc->pq = pq;
             sc->alpha = alpha;
+            sc->jcur = j;
             if (!finite(pq)) {
                 sc->status = ST_NONFINITE;
                 sc->done = 1;
@@ -180,7 +202,6 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
             }
         }
     }
-    const int c = blockIdx.x;
     const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * ND;
     constexpr int NV = 1 + (NQ > 0 ? NQ : 1);
     double v[NV];
@@ -271,20 +292,22 @@ __device__ inline void tile_mac(const typename Ld<E>::V (&tv)[RPT], bool stored,
     }
 }
 
-// Coarse residual entry gi = (coarse element, basis index): the sum of the
-// restriction shares of the coarse element's update chunks, in chunk order.
-__device__ inline double coarse_r0(const SchwarzArgs &a, int gi) {
+// Entry gi of the coarse residual of batch system b (coarse element, basis
+// index): the sum of the restriction shares of the coarse element's update
+// chunks, in chunk order.
+__device__ inline double coarse_r0(const SchwarzArgs &a, int b, int gi) {
     const int nq = a.nq0;
-    const int cc = gi / nq, j = gi - cc * nq;
+    const int cl = gi / nq, j = gi - cl * nq;
+    const int cc = a.csys_ce0[b] + cl;
     double v = 0.0;
     for (int ch = a.cchunk_ptr[cc]; ch < a.cchunk_ptr[cc + 1]; ++ch) v += a.r0part[ch * nq + j];
     return v;
 }
 
-// Entry gi of the input vector of system s (local: r on the subdomain's dofs;
-// coarse: r0).
+// Entry gi of the input vector of dense system s (local: r on the
+// subdomain's dofs; coarse: r0 of its batch system).
 __device__ inline double sys_input(const SchwarzArgs &a, int s, bool coarse, int64_t dof0, int gi) {
-    if (coarse) return coarse_r0(a, gi);
+    if (coarse) return coarse_r0(a, s - a.n_sub, gi);
     if (dof0 >= 0) return a.r[dof0 + gi];
     const int nd = a.nd;
     const int le = gi / nd, i = gi - le * nd;
@@ -441,7 +464,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
 
 template <typename EL, typename EC>
 __global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a, int max_nj) {
-    if (a.mode != 0 && a.sc->done) return;
+    if (a.mode != 0 && a.sc[a.item_owner[blockIdx.x]].done) return;
     extern __shared__ double smem[];
     __shared__ double yout[TILE];
     const int item = blockIdx.x, tid = threadIdx.x;
@@ -494,23 +517,45 @@ __device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) 
 
 template <int NQ>
 __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
-    DevScalars *sc = a.sc;
-    if (a.mode != 0 && sc->done) return;
+    const int nd = a.nd;
+    const int64_t n = a.n_elem * nd;
+    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    const int64_t i1 = (i0 + 256 < n ? i0 + 256 : n) - 1;
+    const int64_t idx = i0 + threadIdx.x;
+    const int my = idx < n ? a.elem_sys[idx / nd] : -1;
     double beta = 0.0;
+    bool active = a.mode == 0 && my >= 0;
     if (a.mode != 0) {
-        const double rz = block_sum_partials<256>(a.itemdot, a.n_items, 1, 0);
-        if (a.mode == 2) beta = rz / sc->rz[(a.iter - 1) & 1];
-        if (blockIdx.x == 0) {
-            const double rr = block_sum_partials<256>(a.rrpart, a.n_rr, 1, 0);
+        // every system with dofs in this block, in turn
+        const int s_lo = a.elem_sys[i0 / nd], s_hi = a.elem_sys[i1 / nd];
+        for (int b = s_lo; b <= s_hi; ++b) {
+            DevScalars *sc = a.sc + b;
+            // the owner block may set `done` during this launch
+            if (block_bcast<256>(threadIdx.x == 0 ? sc->done : 0)) continue;
+            const int it0 = a.rng.item[b];
+            const double rz = block_sum_partials<256>(a.itemdot + it0, a.rng.item[b + 1] - it0, 1, 0);
+            const int j = a.mode == 2 ? sc->jcur : 0;
+            const double bt = a.mode == 2 ? rz / sc->rz[(j - 1) & 1] : 0.0;
+            if (my == b) {
+                beta = bt;
+                active = true;
+            }
+            if (a.rng.owner[b] != (int)blockIdx.x) continue;
+            // owner: close iteration j of system b
+            const int u0 = a.rng.upd[b];
+            const double rr = block_sum_partials<256>(a.rrpart + u0, a.rng.upd[b + 1] - u0, 1, 0);
             double bb = 0.0;
-            if (a.mode == 1) bb = block_sum_partials<256>(a.bbpart, a.n_bb, 2, 0);
+            if (a.mode == 1) {
+                const int g0 = a.rng.spmv[b];
+                bb = block_sum_partials<256>(a.bbpart + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 0);
+            }
             if (threadIdx.x == 0) {
                 if (a.mode == 1) sc->bb = bb;
                 bb = sc->bb;
                 sc->rr = rr;
-                sc->rz[a.iter & 1] = rz;
-                sc->beta = beta;
-                sc->iters = a.iter;
+                sc->rz[j & 1] = rz;
+                sc->beta = bt;
+                sc->iters = j;
                 if (a.mode == 1 && bb == 0.0) {
                     sc->status = ST_ZERO_RHS;
                     sc->done = 1;
@@ -523,35 +568,37 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
                 } else if (!(rz > 0.0)) {
                     sc->status = ST_BREAKDOWN;
                     sc->done = 1;
-                } else if (a.iter >= sc->maxit) {
+                } else if (j >= sc->maxit) {
                     sc->status = ST_NOCONV;
                     sc->done = 1;
                 }
             }
         }
     }
-    const int64_t n = a.n_elem * a.nd;
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n) return;
+    if (!active) return;
     const int dr = a.dof_rt[idx];
     double zz = tile_row_value(a, dr >> 6, dr & 63);
     if (NQ > 0) {
-        const int64_t e = idx / a.nd;
-        const int c0 = a.elem_coarse[e] * NQ;
+        const int64_t e = idx / nd;
+        const int g0 = (a.elem_coarse[e] - a.csys_ce0[my]) * NQ;
+        const int rt0 = a.coarse_rt0[my];
         const double *Pr = a.P + idx * NQ;
 #pragma unroll
         for (int j = 0; j < NQ; ++j) {
-            const int gi = c0 + j;
-            zz = fma(Pr[j], tile_row_value(a, a.coarse_rt0 + (gi >> 6), gi & 63), zz);
+            const int gi = g0 + j;
+            zz = fma(Pr[j], tile_row_value(a, rt0 + (gi >> 6), gi & 63), zz);
         }
     }
     if (a.mode == 2) zz = fma(beta, a.p[idx], zz);
     a.p[idx] = zz;
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double *part, int n, int slot, double *out) {
-    const double t = block_sum_partials<256>(part, n, 2, slot);
-    if (threadIdx.x == 0) *out = t;
+// sc[b].tr = sum of the SpMV partials (slot `slot`) of system b; one block per system.
+__global__ __launch_bounds__(256) void k_sum_partials(const double *part, const int32_t *ranges, int slot,
+                                                      DevScalars *sc) {
+    const int b = blockIdx.x, g0 = ranges[b];
+    const double t = block_sum_partials<256>(part + 2 * (int64_t)g0, ranges[b + 1] - g0, 2, slot);
+    if (threadIdx.x == 0) sc[b].tr = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -771,7 +818,7 @@ __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
     if (lane < ND) a.I[e * ND + lane] = accI;
     if (bad) s_bad = 1;
     __syncthreads();
-    if (lane == 0 && s_bad) a.sc->ionic_bad = 1;
+    if (lane == 0 && s_bad) *a.bad = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -787,37 +834,50 @@ __global__ void k_project_p0(const double *vals, int ncomp, int64_t n_elem, int 
     }
 }
 
-__global__ void k_zero(double *x, int64_t n) {
+// out = x, with the dofs of systems stopped on a zero right-hand side set to 0.
+__global__ void k_finish(const double *x, double *out, const int32_t *elem_sys, int nd, int64_t n_elem,
+                         const DevScalars *sc) {
+    const int64_t n = n_elem * nd;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        x[t] = 0.0;
+        out[t] = sc[elem_sys[t / nd]].status == ST_ZERO_RHS ? 0.0 : x[t];
 }
 
-__global__ void k_status_reset(DevScalars *sc, double tol2, int maxit, int reset_ionic) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (reset_ionic) sc->ionic_bad = 0;
-        sc->bb = sc->rr = sc->pq = sc->alpha = sc->beta = sc->tr = 0.0;
-        sc->rz[0] = sc->rz[1] = 0.0;
-        sc->tol2 = tol2;
-        sc->done = 0;
-        sc->status = ST_RUN;
-        sc->iters = 0;
-        sc->maxit = maxit;
+__global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit, int reset_ionic) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_sys; b += gridDim.x * blockDim.x) {
+        DevScalars &d = sc[b];
+        if (reset_ionic) d.ionic_bad = 0;
+        d.bb = d.rr = d.pq = d.alpha = d.beta = d.tr = 0.0;
+        d.rz[0] = d.rz[1] = 0.0;
+        d.tol2 = tol2;
+        d.done = 0;
+        d.status = ST_RUN;
+        d.iters = 0;
+        d.jcur = 0;
+        d.maxit = maxit;
     }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
-constexpr int kSpmvWPG = 4;
-
-int spmv_blocks(const DevMatrix &A) { return (int)A.n_groups; }
-
-template <int ND>
-static hipError_t spmv_nd(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv<ND, kSpmvWPG>), dim3(spmv_blocks(A)), dim3(64 * kSpmvWPG), 0, s, A, a);
+template <int ND, int WPG>
+static hipError_t spmv_nd_w(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_spmv<ND, WPG>), dim3((unsigned)A.n_groups), dim3(64 * WPG), 0, s, A, a);
     return hipGetLastError();
 }
 
+template <int ND>
+static hipError_t spmv_nd(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
+    switch (A.wpg) {
+    case 1: return spmv_nd_w<ND, 1>(A, a, s);
+    case 2: return spmv_nd_w<ND, 2>(A, a, s);
+    case 4: return spmv_nd_w<ND, 4>(A, a, s);
+    case 8: return spmv_nd_w<ND, 8>(A, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
+    if (A.n_groups <= 0) return hipSuccess;
     switch (A.nd) {
     case 3: return spmv_nd<3>(A, a, s);
     case 4: return spmv_nd<4>(A, a, s);
@@ -842,6 +902,7 @@ static hipError_t update_nd(const UpdateArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_update(const UpdateArgs &a, hipStream_t s) {
+    if (a.n_grp <= 0) return hipSuccess;
     switch (a.nd) {
     case 3: return update_nd<3>(a, s);
     case 4: return update_nd<4>(a, s);
@@ -860,22 +921,38 @@ template <typename E> static constexpr size_t scratch_bytes() {
     return (size_t)256 * RPT * acc_size<E>();
 }
 
+// x (FP64, columns + row I), x in the accumulation type, column exchange
+// [2][4][64]; the final row reduction (256 * RPT values) reuses the same space
+static size_t lds_need(size_t acc, size_t scratch, int max_nj) {
+    size_t b = (size_t)(max_nj + 1) * TILE * 8 + (acc == 8 ? 0 : (size_t)(max_nj + 1) * TILE * acc);
+    b = (b + 15) & ~(size_t)15;
+    const size_t x_end = (acc == 8 ? 1 : 3) * (size_t)(max_nj + 1) * TILE * acc;  // offset of the exchange area
+    if (x_end > b) b = x_end;
+    b += 2 * 4 * TILE * acc;
+    return b > scratch ? b : scratch;
+}
+
+template <typename EL, typename EC>
+static size_t schwarz_bytes_t(int max_nj) {
+    const size_t bl = lds_need(acc_size<EL>(), scratch_bytes<EL>(), max_nj);
+    const size_t bc = lds_need(acc_size<EC>(), scratch_bytes<EC>(), max_nj);
+    return bl > bc ? bl : bc;
+}
+
 template <typename EL, typename EC>
 static hipError_t schwarz_t(const SchwarzArgs &a, int n_items, int max_nj, hipStream_t s) {
-    // x (FP64, columns + row I), x in the accumulation type, column exchange [2][4][64];
-    // the final row reduction (256 * RPT values) reuses the same space
-    auto need = [&](size_t acc, size_t scratch) {
-        size_t b = (size_t)(max_nj + 1) * TILE * 8 + (acc == 8 ? 0 : (size_t)(max_nj + 1) * TILE * acc);
-        b = (b + 15) & ~(size_t)15;
-        size_t x_end = (acc == 8 ? 1 : 3) * (size_t)(max_nj + 1) * TILE * acc;  // offset of the exchange area
-        if (x_end > b) b = x_end;
-        b += 2 * 4 * TILE * acc;
-        return b > scratch ? b : scratch;
-    };
-    const size_t bl = need(acc_size<EL>(), scratch_bytes<EL>()), bc = need(acc_size<EC>(), scratch_bytes<EC>());
-    const size_t bytes = bl > bc ? bl : bc;
-    hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_items), dim3(256), bytes, s, a, max_nj);
+    const size_t lds = schwarz_bytes_t<EL, EC>(max_nj);
+    hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_items), dim3(256), lds, s, a, max_nj);
     return hipGetLastError();
+}
+
+size_t schwarz_lds_bytes(int local_store, int coarse_store, int max_nj) {
+    const size_t l = local_store == STORE_F64 ? schwarz_bytes_t<double, double>(max_nj)
+                     : local_store == STORE_F32 ? schwarz_bytes_t<float, float>(max_nj)
+                                                : schwarz_bytes_t<uint16_t, float>(max_nj);
+    const size_t c = coarse_store == STORE_F64 ? schwarz_bytes_t<double, double>(max_nj)
+                                               : schwarz_bytes_t<float, float>(max_nj);
+    return l > c ? l : c;
 }
 
 hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store, int max_nj,
@@ -898,7 +975,9 @@ hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, in
 }
 
 hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s) {
-    const int blocks = (int)((a.n_elem * a.nd + 255) / 256);
+    const int64_t n = a.n_elem * a.nd;
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256);
     switch (a.nq0) {
     case 0: hipLaunchKernelGGL((k_pupdate<0>), dim3(blocks), dim3(256), 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_pupdate<3>), dim3(blocks), dim3(256), 0, s, a); break;
@@ -908,12 +987,15 @@ hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const double *part, int n, int slot, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, n, slot, out);
+hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_sys, int slot, DevScalars *sc,
+                               hipStream_t s) {
+    if (n_sys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_partials, dim3(n_sys), dim3(256), 0, s, part, ranges, slot, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_ionic(const IonicArgs &a, hipStream_t s) {
+    if (a.n_elem <= 0) return hipSuccess;
     const dim3 g((unsigned)a.n_elem), b(64);
 #define PDG_IONIC(D, P)                                                  \
     if (a.dim == D && a.p == P) {                                        \
@@ -926,23 +1008,26 @@ hipError_t launch_ionic(const IonicArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+static int grid_for(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
 hipError_t launch_project_p0(const double *vals, int ncomp, int64_t n_elem, int nd, const double *norm,
                              double *coeff, hipStream_t s) {
-    const int64_t total = (int64_t)ncomp * n_elem * nd;
-    const int blocks = (int)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
-    hipLaunchKernelGGL(k_project_p0, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, vals, ncomp, n_elem, nd,
-                       norm, coeff);
+    hipLaunchKernelGGL(k_project_p0, dim3(grid_for((int64_t)ncomp * n_elem * nd)), dim3(256), 0, s, vals, ncomp,
+                       n_elem, nd, norm, coeff);
     return hipGetLastError();
 }
 
-hipError_t launch_zero(double *x, int64_t n, hipStream_t s) {
-    const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    hipLaunchKernelGGL(k_zero, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, x, n);
+hipError_t launch_finish(const double *x, double *out, const int32_t *elem_sys, int nd, int64_t n_elem,
+                         const DevScalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(grid_for(n_elem * nd)), dim3(256), 0, s, x, out, elem_sys, nd, n_elem, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_status_reset(DevScalars *sc, double tol2, int maxit, int reset_ionic, hipStream_t s) {
-    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, sc, tol2, maxit, reset_ionic);
+hipError_t launch_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit, int reset_ionic, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_reset, dim3(grid_for(n_sys)), dim3(256), 0, s, sc, n_sys, tol2, maxit, reset_ionic);
     return hipGetLastError();
 }
 

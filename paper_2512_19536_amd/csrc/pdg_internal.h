@@ -70,23 +70,27 @@ struct DenseSys {
 
 struct Precond {
     int n_sub = 0, n_coarse = 0, q = 0, nq0 = 0;
+    int n_bsys = 1;                                // independent systems of the batch
     int local_prec = PDG_F64, coarse_prec = PDG_F64;
     std::vector<int32_t> sub_ptr, sub_elems;       // CSR of elements per subdomain
-    std::vector<int32_t> coarse_ptr, coarse_elems; // CSR of elements per coarse element
-    std::vector<int32_t> elem_coarse;
-    std::vector<DenseSys> sys;                     // n_sub local systems (+1 coarse last)
+    std::vector<int32_t> sub_bsys;                 // batch system of each subdomain
+    // coarse elements in internal numbering (those of one batch system contiguous)
+    std::vector<int32_t> coarse_orig, cnum;        // internal -> caller label, caller label -> internal
+    std::vector<int32_t> csys_ce0;                 // [n_bsys+1] first internal coarse element of each system
+    std::vector<int32_t> coarse_ptr, coarse_elems; // CSR of elements per (internal) coarse element
+    std::vector<int32_t> elem_coarse;              // internal coarse element of each element
+    std::vector<DenseSys> sys;                     // n_sub local systems, then one coarse system per batch system
     std::vector<double> inv64;                     // FP64 inverse tiles (all systems)
     int64_t n_tiles = 0;
     std::vector<double> P;                         // [n_elem][nd][nq0]
-    std::vector<double> K0;                        // [N0][N0]
-    int64_t N0 = 0;
-    // work items of the Schwarz kernel: (system, row tile), longest first
-    std::vector<int32_t> item_sys, item_row;
-    std::vector<double> local_inv_dense_cache;     // unused; kept empty
+    std::vector<std::vector<double>> K0blk;        // K0 of each batch system, internal order
+    int64_t N0 = 0;                                // coarse dofs over all systems
 };
 
+// elem_bsys: batch system of every element (all 0 for one system).
 void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
-                   const pdg_precond_desc *d, Precond &pc, int n_threads);
+                   const pdg_precond_desc *d, const std::vector<int32_t> &elem_bsys, int n_bsys, Precond &pc,
+                   int n_threads);
 void dense_inverse_of_system(const Precond &pc, int s, std::vector<double> &out);
 
 }  // namespace pdg

@@ -126,7 +126,8 @@ void dense_inverse_of_system(const Precond &pc, int s, std::vector<double> &out)
 }
 
 void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
-                   const pdg_precond_desc *d, Precond &pc, int n_threads) {
+                   const pdg_precond_desc *d, const std::vector<int32_t> &elem_bsys, int n_bsys, Precond &pc,
+                   int n_threads) {
     if (!d || d->n_sub < 1 || !d->elem_sub) throw Error(PDG_EINVAL, "bad preconditioner descriptor");
     const int64_t n = m.n_elem;
     const int nd = m.nd, dim = m.dim;
@@ -139,6 +140,7 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
     pc.local_prec = d->local_prec;
     pc.coarse_prec = d->coarse_prec;
     pc.q = d->coarse_q;
+    pc.n_bsys = n_bsys;
 
     // subdomain CSR (elements in ascending order inside a subdomain)
     std::vector<int32_t> cnt(pc.n_sub, 0);
@@ -161,10 +163,17 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
         pos[e] = fill[s] - pc.sub_ptr[s];
         pc.sub_elems[fill[s]++] = (int32_t)e;
     }
+    pc.sub_bsys.assign(pc.n_sub, 0);
+    for (int s = 0; s < pc.n_sub; ++s) {
+        const int b = elem_bsys[pc.sub_elems[pc.sub_ptr[s]]];
+        for (int k = pc.sub_ptr[s]; k < pc.sub_ptr[s + 1]; ++k)
+            if (elem_bsys[pc.sub_elems[k]] != b) throw Error(PDG_EINVAL, "a subdomain spans two systems");
+        pc.sub_bsys[s] = b;
+    }
 
     // system table: locals then (optionally) the coarse system
     const bool coarse = pc.q > 0;
-    pc.sys.resize(pc.n_sub + (coarse ? 1 : 0));
+    pc.sys.resize(pc.n_sub + (coarse ? n_bsys : 0));
     int64_t toff = 0;
     for (int s = 0; s < pc.n_sub; ++s) {
         DenseSys &S = pc.sys[s];
@@ -175,25 +184,42 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
     }
 
     // coarse space
-    std::vector<double> K0;
     if (coarse) {
         const int32_t *ec = d->elem_coarse ? d->elem_coarse : d->elem_sub;
         pc.n_coarse = d->elem_coarse ? d->n_coarse : d->n_sub;
         if (pc.n_coarse < 1) throw Error(PDG_EINVAL, "n_coarse < 1");
-        pc.elem_coarse.assign(ec, ec + n);
-        std::vector<int32_t> cc(pc.n_coarse, 0);
+        std::vector<int32_t> cc(pc.n_coarse, 0), cb(pc.n_coarse, -1);
         for (int64_t e = 0; e < n; ++e) {
             if (ec[e] < 0 || ec[e] >= pc.n_coarse) throw Error(PDG_EINVAL, "elem_coarse label out of range");
             cc[ec[e]]++;
+            if (cb[ec[e]] < 0) cb[ec[e]] = elem_bsys[e];
+            else if (cb[ec[e]] != elem_bsys[e]) throw Error(PDG_EINVAL, "a coarse element spans two systems");
         }
-        pc.coarse_ptr.assign(pc.n_coarse + 1, 0);
-        for (int c = 0; c < pc.n_coarse; ++c) {
+        for (int c = 0; c < pc.n_coarse; ++c)
             if (cc[c] == 0) throw Error(PDG_EINVAL, "empty coarse element");
-            pc.coarse_ptr[c + 1] = pc.coarse_ptr[c] + cc[c];
+        // internal numbering: coarse elements of one system are contiguous
+        // (stable in the caller's label order)
+        pc.coarse_orig.resize(pc.n_coarse);
+        std::iota(pc.coarse_orig.begin(), pc.coarse_orig.end(), 0);
+        std::stable_sort(pc.coarse_orig.begin(), pc.coarse_orig.end(),
+                         [&](int32_t a, int32_t b) { return cb[a] < cb[b]; });
+        pc.cnum.assign(pc.n_coarse, 0);
+        for (int k = 0; k < pc.n_coarse; ++k) pc.cnum[pc.coarse_orig[k]] = k;
+        pc.csys_ce0.assign(n_bsys + 1, 0);
+        for (int c = 0; c < pc.n_coarse; ++c) pc.csys_ce0[cb[c] + 1]++;
+        for (int b = 0; b < n_bsys; ++b) {
+            if (pc.csys_ce0[b + 1] == 0) throw Error(PDG_EINVAL, "a system has no coarse element");
+            pc.csys_ce0[b + 1] += pc.csys_ce0[b];
         }
+        pc.elem_coarse.resize(n);
+        for (int64_t e = 0; e < n; ++e) pc.elem_coarse[e] = pc.cnum[ec[e]];
+        std::vector<int32_t> ccnt(pc.n_coarse, 0);
+        for (int64_t e = 0; e < n; ++e) ccnt[pc.elem_coarse[e]]++;
+        pc.coarse_ptr.assign(pc.n_coarse + 1, 0);
+        for (int c = 0; c < pc.n_coarse; ++c) pc.coarse_ptr[c + 1] = pc.coarse_ptr[c] + ccnt[c];
         pc.coarse_elems.assign(n, 0);
         std::vector<int32_t> cf(pc.coarse_ptr.begin(), pc.coarse_ptr.end() - 1);
-        for (int64_t e = 0; e < n; ++e) pc.coarse_elems[cf[ec[e]]++] = (int32_t)e;
+        for (int64_t e = 0; e < n; ++e) pc.coarse_elems[cf[pc.elem_coarse[e]]++] = (int32_t)e;
         // coarse bounding boxes
         std::vector<double> clo(pc.n_coarse * dim, 1e300), chi(pc.n_coarse * dim, -1e300);
         for (int64_t e = 0; e < n; ++e)
@@ -233,12 +259,20 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
                     PK[i * nq0 + j] = s;
                 }
         }, n_threads);
-        // K0 = P^T K P, accumulated row-block by row-block of K
+        // K0 = P^T K P (one dense block per batch system), accumulated
+        // row-block by row-block of K
         pc.N0 = (int64_t)pc.n_coarse * nq0;
-        const int64_t N0 = pc.N0;
-        K0.assign(N0 * N0, 0.0);
+        pc.K0blk.assign(n_bsys, {});
+        for (int b = 0; b < n_bsys; ++b) {
+            const int64_t n0 = (int64_t)(pc.csys_ce0[b + 1] - pc.csys_ce0[b]) * nq0;
+            if (n0 > kMaxLocalDofs) throw Error(PDG_EINVAL, "coarse system exceeds 6144 dofs");
+            pc.K0blk[b].assign(n0 * n0, 0.0);
+        }
         std::vector<double> KP(nd * nq0);
         for (int64_t e = 0; e < n; ++e) {
+            const int b = elem_bsys[e];
+            const int64_t n0 = (int64_t)(pc.csys_ce0[b + 1] - pc.csys_ce0[b]) * nq0;
+            double *K0 = pc.K0blk[b].data();
             const double *Pe = &pc.P[e * nd * nq0];
             for (int64_t k = K.row_ptr[e]; k < K.row_ptr[e + 1]; ++k) {
                 const int64_t o = K.col[k];
@@ -250,26 +284,30 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
                         for (int t = 0; t < nd; ++t) s += Kb[i * nd + t] * Po[t * nq0 + j];
                         KP[i * nq0 + j] = s;
                     }
-                const int64_t r0 = (int64_t)ec[e] * nq0, c0 = (int64_t)ec[o] * nq0;
+                const int64_t r0 = (int64_t)(pc.elem_coarse[e] - pc.csys_ce0[b]) * nq0;
+                const int64_t c0 = (int64_t)(pc.elem_coarse[o] - pc.csys_ce0[b]) * nq0;
                 for (int a = 0; a < nq0; ++a)
-                    for (int b = 0; b < nq0; ++b) {
+                    for (int bb = 0; bb < nq0; ++bb) {
                         double s = 0;
-                        for (int i = 0; i < nd; ++i) s += Pe[i * nq0 + a] * KP[i * nq0 + b];
-                        K0[(r0 + a) * N0 + c0 + b] += s;
+                        for (int i = 0; i < nd; ++i) s += Pe[i * nq0 + a] * KP[i * nq0 + bb];
+                        K0[(r0 + a) * n0 + c0 + bb] += s;
                     }
             }
         }
-        for (int64_t i = 0; i < N0; ++i)
-            for (int64_t j = 0; j < i; ++j) {
-                double s = 0.5 * (K0[i * N0 + j] + K0[j * N0 + i]);
-                K0[i * N0 + j] = K0[j * N0 + i] = s;
-            }
-        pc.K0 = K0;
-        DenseSys &S = pc.sys[pc.n_sub];
-        S.n = N0;
-        S.nt = (N0 + kTile - 1) / kTile;
-        S.tile_off = toff;
-        toff += S.nt * (S.nt + 1) / 2;
+        for (int b = 0; b < n_bsys; ++b) {
+            double *K0 = pc.K0blk[b].data();
+            const int64_t n0 = (int64_t)(pc.csys_ce0[b + 1] - pc.csys_ce0[b]) * nq0;
+            for (int64_t i = 0; i < n0; ++i)
+                for (int64_t j = 0; j < i; ++j) {
+                    double s = 0.5 * (K0[i * n0 + j] + K0[j * n0 + i]);
+                    K0[i * n0 + j] = K0[j * n0 + i] = s;
+                }
+            DenseSys &S = pc.sys[pc.n_sub + b];
+            S.n = n0;
+            S.nt = (n0 + kTile - 1) / kTile;
+            S.tile_off = toff;
+            toff += S.nt * (S.nt + 1) / 2;
+        }
     }
     pc.n_tiles = toff;
     pc.inv64.assign(pc.n_tiles * kTile * kTile, 0.0);
@@ -292,24 +330,13 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
         spd_inverse(ni, D.data());
         store_tiles(D.data(), ni, &pc.inv64[pc.sys[s].tile_off * kTile * kTile]);
     }, n_threads);
-    if (coarse) {
-        spd_inverse(pc.N0, K0.data());
-        store_tiles(K0.data(), pc.N0, &pc.inv64[pc.sys[pc.n_sub].tile_off * kTile * kTile]);
-    }
-
-    // work items (system, row tile), longest rows first (LPT order)
-    std::vector<std::pair<int64_t, int64_t>> items;
-    for (size_t s = 0; s < pc.sys.size(); ++s)
-        for (int64_t I = 0; I < pc.sys[s].nt; ++I) items.push_back({(int64_t)s, I});
-    std::stable_sort(items.begin(), items.end(), [&](const auto &a, const auto &b) {
-        return pc.sys[a.first].nt > pc.sys[b.first].nt;
-    });
-    pc.item_sys.clear();
-    pc.item_row.clear();
-    for (auto &it : items) {
-        pc.item_sys.push_back((int32_t)it.first);
-        pc.item_row.push_back((int32_t)it.second);
-    }
+    if (coarse)
+        parallel_for(n_bsys, [&](int64_t b) {
+            std::vector<double> D = pc.K0blk[b];
+            const DenseSys &S = pc.sys[pc.n_sub + b];
+            spd_inverse(S.n, D.data());
+            store_tiles(D.data(), S.n, &pc.inv64[S.tile_off * kTile * kTile]);
+        }, n_threads);
 }
 
 }  // namespace pdg

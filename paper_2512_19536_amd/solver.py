@@ -10,7 +10,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import PdgMesh, PdgPrecondDesc, PdgSolveInfo, check
+from ._lib import PdgMesh, PdgPrecondDesc, PdgSolveInfo, PdgTuneResult, check
 
 
 def _ptr(a):
@@ -69,6 +69,10 @@ class Context:
                     facet_elem=_ptr(arr["facet_elem"]), facet_geom=_ptr(arr["facet_geom"]),
                     facet_normal=_ptr(arr["facet_normal"]), sigma=_ptr(arr["sigma"]))
         self._call("pdg_set_mesh", ctypes.byref(m), int(p))
+
+    def set_systems(self, elem_ptr):
+        ep = np.ascontiguousarray(elem_ptr, dtype=np.int64)
+        self._call("pdg_set_systems", len(ep) - 1, _ptr(ep))
 
     def get_sizes(self):
         n_elem, nd, n_dof, nnzb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
@@ -137,6 +141,11 @@ class Context:
     def set_option(self, option, value):
         self._call("pdg_set_option", int(option), int(value))
 
+    def autotune(self, reps=20):
+        res = PdgTuneResult()
+        self._call("pdg_autotune", int(reps), ctypes.byref(res))
+        return res.as_dict()
+
     def kernel_timing(self):
         n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         self._call("pdg_kernel_timing", ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by))
@@ -172,15 +181,39 @@ class Context:
         check(self._ctx, st)
         return info.as_dict()
 
+    def system_info(self, sys):
+        info, st = PdgSolveInfo(), ctypes.c_int32()
+        self._call("pdg_get_system_info", int(sys), ctypes.byref(info), ctypes.byref(st))
+        d = info.as_dict()
+        d["status"] = st.value
+        return d
 
-def from_problem(problem, device="cuda:0", local_prec=None, coarse_prec=None, bind=True, options=None):
+
+def step_batch(ctxs, us, u_prevs, ions, tol, maxit, f_ext=None):
+    """pdg_step_batch over several contexts (each on its own stream)."""
+    n = len(ctxs)
+    lib = ctxs[0].lib
+    arr = lambda xs: (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])  # noqa: E731
+    cs = (ctypes.c_void_p * n)(*[c._ctx.value for c in ctxs])
+    infos = (PdgSolveInfo * n)()
+    st = lib.pdg_step_batch(cs, n, arr(us), arr(u_prevs), arr(ions), None if f_ext is None else arr(f_ext),
+                            float(tol), int(maxit), infos)
+    check(ctxs[0]._ctx, st)
+    return [i.as_dict() for i in infos]
+
+
+def from_problem(problem, device="cuda:0", local_prec=None, coarse_prec=None, bind=True, options=None,
+                 stream=None):
     """Context set up for a workload object with the attributes of
-    ``pdg_inputs.problems.Problem`` (mesh, p, constants, partitions, ionic).
+    ``pdg_inputs.problems.Problem`` (mesh, p, constants, partitions, ionic;
+    optionally ``elem_ptr`` for a batch of independent systems).
     ``options``: {pdg option id: value} applied right after creation."""
-    ctx = Context(device)
+    ctx = Context(device, stream)
     for k, v in (options or {}).items():
         ctx.set_option(k, v)
     ctx.set_mesh(problem.mesh, problem.p)
+    if getattr(problem, "elem_ptr", None) is not None:
+        ctx.set_systems(problem.elem_ptr)
     ctx.assemble(problem.chi_m, problem.c_m, problem.dt, problem.eta0)
     ctx.set_ionic(problem.ionic)
     ctx.setup_preconditioner(problem.elem_sub, problem.elem_coarse, problem.coarse_q,
@@ -196,10 +229,57 @@ def initial_state(ctx, problem):
     torch = ctx.torch
     dev = ctx.device
     n, nd = problem.n_elem, problem.nd
-    u_vals = torch.tensor(np.asarray(problem.u0_elem, dtype=np.float64), device=dev)
-    y_vals = torch.tensor(np.ascontiguousarray(problem.y0_elem, dtype=np.float64), device=dev)
-    U = torch.empty(n * nd, dtype=torch.float64, device=dev)
-    Y = torch.empty(y_vals.shape[0] * n * nd, dtype=torch.float64, device=dev)
-    ctx.project_p0(u_vals.unsqueeze(0), U)
-    ctx.project_p0(y_vals, Y)
-    return U, U.clone(), Y
+    with torch.cuda.stream(ctx.stream):
+        u_vals = torch.tensor(np.asarray(problem.u0_elem, dtype=np.float64), device=dev)
+        y_vals = torch.tensor(np.ascontiguousarray(problem.y0_elem, dtype=np.float64), device=dev)
+        U = torch.empty(n * nd, dtype=torch.float64, device=dev)
+        Y = torch.empty(y_vals.shape[0] * n * nd, dtype=torch.float64, device=dev)
+        ctx.project_p0(u_vals.unsqueeze(0), U)
+        ctx.project_p0(y_vals, Y)
+        Up = U.clone()
+    ctx.stream.synchronize()
+    return U, Up, Y
+
+
+class BatchSolver:
+    """A batch of independent systems (``pdg_inputs.problems.Batch``): one
+    context per polynomial degree holding that degree's systems, each context
+    on its own stream (or all on the current stream), stepped together by
+    pdg_step_batch."""
+
+    def __init__(self, batch, device="cuda:0", options=None, separate_streams=True):
+        import torch
+        self.batch = batch
+        self.ctxs, self.problems, self.members = [], [], []
+        for p, (pr, idx) in sorted(batch.groups.items()):
+            st = torch.cuda.Stream(device=device) if separate_streams else None
+            self.ctxs.append(from_problem(pr, device=device, options=options, stream=st))
+            self.problems.append(pr)
+            self.members.append(idx)
+        # system k -> (context index, system index inside the context)
+        self.where = {}
+        for ci, idx in enumerate(self.members):
+            for s, k in enumerate(idx):
+                self.where[k] = (ci, s)
+
+    def set_option(self, option, value):
+        for c in self.ctxs:
+            c.set_option(option, value)
+
+    def initial_state(self):
+        st = [initial_state(c, pr) for c, pr in zip(self.ctxs, self.problems)]
+        return [list(x) for x in zip(*st)]  # [U list, Up list, Y list]
+
+    def step(self, U, Up, Y, tol, maxit):
+        return step_batch(self.ctxs, U, Up, Y, tol, maxit)
+
+    def system_slice(self, k):
+        """(context index, dof slice) of system k inside its context's vectors."""
+        ci, s = self.where[k]
+        ep = self.problems[ci].elem_ptr
+        nd = self.problems[ci].nd
+        return ci, slice(int(ep[s]) * nd, int(ep[s + 1]) * nd)
+
+    def system_info(self, k):
+        ci, s = self.where[k]
+        return self.ctxs[ci].system_info(s)

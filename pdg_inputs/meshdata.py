@@ -93,3 +93,27 @@ class Mesh:
             facet_normal=np.ascontiguousarray(self.facet_normal, dtype=np.float64),
             sigma=np.ascontiguousarray(sig, dtype=np.float64),
         )
+
+
+def concat_meshes(meshes):
+    """Disjoint union of meshes of one dimension: elements, sub-cells and
+    facets of mesh k follow those of meshes 0..k-1 (element indices shifted).
+    Returns the union and elem_ptr, the element range of every input mesh."""
+    dim = meshes[0].dim
+    assert all(m.dim == dim for m in meshes)
+    n_el = np.array([m.n_elem for m in meshes], dtype=np.int64)
+    elem_ptr = np.concatenate([[0], np.cumsum(n_el)]).astype(np.int64)
+    n_cell = np.array([m.n_cell for m in meshes], dtype=np.int64)
+    cell_off = np.concatenate([[0], np.cumsum(n_cell)])[:-1]
+    cell_ptr = np.concatenate([[0]] + [m.cell_ptr[1:] + o for m, o in zip(meshes, cell_off)]).astype(np.int64)
+    facet_elem = np.concatenate([np.where(m.facet_elem >= 0, m.facet_elem + o, -1)
+                                 for m, o in zip(meshes, elem_ptr[:-1])]).astype(np.int64)
+    sig = [m.sigma if m.sigma is not None else np.broadcast_to(np.eye(dim), (m.n_elem, dim, dim)) for m in meshes]
+    reg = [m.region if m.region is not None else np.zeros(m.n_elem, np.int32) for m in meshes]
+    out = Mesh(dim=dim, cell_ptr=cell_ptr,
+               cell_geom=np.concatenate([m.cell_geom for m in meshes]),
+               facet_elem=facet_elem,
+               facet_geom=np.concatenate([m.facet_geom for m in meshes]),
+               facet_normal=np.concatenate([m.facet_normal for m in meshes]),
+               region=np.concatenate(reg), sigma=np.concatenate(sig))
+    return out, elem_ptr

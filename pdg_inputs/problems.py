@@ -22,6 +22,14 @@ Workloads
 ``cfg3``  64^3 cubes (seed 4), p = 3, dt = 2.5 us, fibre-aligned conductivity
           10:1 along a smooth seeded random fibre field (seed 5), 512
           subdomains (seed 6), FP32 Schwarz solves.
+``cfg4``  a batch of 64 independent 3-D problems: target sizes N log-uniform
+          in [2k, 60k] dofs and degrees p uniform in {1..4} (seed 7); each a
+          cube of n^3 cubes of 0.25 mm agglomerated to ~8 cubes per element with
+          n = round((8 N / nd)^(1/3)), the physics of cfg2 (two regions,
+          dt = 2.5 us, planar stimulus), clamp(round(N / 250), 8, 256)
+          subdomains of equal target size (so about 250 dofs each) with the P1
+          coarse space on them, FP32 Schwarz solves.  Systems of one degree are
+          concatenated into one problem (``elem_ptr`` gives the systems).
 ``small3d`` a tiny 3-D problem (6^3 cubes) for quick tests.
 """
 from __future__ import annotations
@@ -33,7 +41,7 @@ import numpy as np
 from . import params
 from .mesh2d import voronoi_mesh
 from .mesh3d import agglomerated_cube_mesh, renumber_elements
-from .meshdata import Mesh
+from .meshdata import Mesh, concat_meshes
 from .partition import order_by_part, quadrants, rcb
 
 
@@ -57,6 +65,7 @@ class Problem:
     local_prec: str = "f64"
     coarse_prec: str = "f64"
     maxit: int = 5000
+    elem_ptr: np.ndarray | None = None   # batch of independent systems: element range of each
 
     @property
     def n_elem(self):
@@ -200,4 +209,74 @@ def small2d(n=24, p=2, seed=5) -> Problem:
                    n_steps=3, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(ne))
 
 
-BUILDERS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3}
+def concat_problems(name, probs) -> Problem:
+    """One problem holding independent systems of one degree side by side
+    (meshes, labels and initial data concatenated; ``elem_ptr`` set)."""
+    p0 = probs[0]
+    for q in probs:
+        assert (q.p, q.dt, q.chi_m, q.c_m, q.eta0, q.coarse_q, q.tol, q.local_prec, q.coarse_prec) == \
+            (p0.p, p0.dt, p0.chi_m, p0.c_m, p0.eta0, p0.coarse_q, p0.tol, p0.local_prec, p0.coarse_prec)
+        assert np.array_equal(q.ionic, p0.ionic)
+    mesh, elem_ptr = concat_meshes([q.mesh for q in probs])
+    sub_off = np.cumsum([0] + [int(q.elem_sub.max()) + 1 for q in probs])
+    crs_off = np.cumsum([0] + [int(q.elem_coarse.max()) + 1 for q in probs])
+    sub = np.concatenate([q.elem_sub + o for q, o in zip(probs, sub_off)]).astype(np.int32)
+    crs = np.concatenate([q.elem_coarse + o for q, o in zip(probs, crs_off)]).astype(np.int32)
+    return Problem(name, mesh, p=p0.p, chi_m=p0.chi_m, c_m=p0.c_m, dt=p0.dt, eta0=p0.eta0,
+                   elem_sub=sub, elem_coarse=crs, coarse_q=p0.coarse_q, n_steps=p0.n_steps, tol=p0.tol,
+                   u0_elem=np.concatenate([q.u0_elem for q in probs]),
+                   y0_elem=np.ascontiguousarray(np.concatenate([q.y0_elem for q in probs], axis=1)),
+                   ionic=p0.ionic.copy(), local_prec=p0.local_prec, coarse_prec=p0.coarse_prec,
+                   maxit=p0.maxit, elem_ptr=elem_ptr)
+
+
+@dataclass
+class Batch:
+    """Independent systems and their grouping by degree (one concatenated
+    problem per degree, systems in generation order inside a group)."""
+    name: str
+    systems: list
+    groups: dict      # p -> (concatenated Problem, [system indices])
+
+    @property
+    def n_dof(self):
+        return sum(q.n_dof for q in self.systems)
+
+
+def nd3(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def cfg4_sizes(n_sys=64, seed=7):
+    """Target dofs and degree of every system of the batch workload."""
+    rng = np.random.default_rng(seed)
+    N = np.exp(rng.uniform(np.log(2000.0), np.log(60000.0), n_sys))
+    ps = rng.integers(1, 5, n_sys)
+    return N, ps
+
+
+def batch_system(i, N, p, n_steps=10, prec="f32") -> Problem:
+    nd = nd3(p)
+    n_grid = max(4, int(round((8.0 * N / nd) ** (1.0 / 3.0))))
+    n_sub = int(np.clip(round(N / 250.0), 8, 256))
+    pr = _cube_problem(f"cfg4_s{i}", n_grid, 0.25 * n_grid, seed_mesh=700 + i, seed_part=800 + i,
+                       n_sub=n_sub, p=p, spread=0.0, sigma_kind="two_region", n_steps=n_steps,
+                       sigma0=SIGMA_3D, dt=DT_3D)
+    pr.local_prec = pr.coarse_prec = prec
+    return pr
+
+
+def make_batch(name, systems) -> Batch:
+    groups = {}
+    for p in sorted({q.p for q in systems}):
+        idx = [i for i, q in enumerate(systems) if q.p == p]
+        groups[p] = (concat_problems(f"{name}_p{p}", [systems[i] for i in idx]), idx)
+    return Batch(name, systems, groups)
+
+
+def cfg4(n_sys=64, seed=7) -> Batch:
+    N, ps = cfg4_sizes(n_sys, seed)
+    return make_batch("cfg4", [batch_system(i, N[i], int(ps[i])) for i in range(n_sys)])
+
+
+BUILDERS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}

@@ -119,3 +119,77 @@ def test_non_spd_conductivity_rejected():
     pr.mesh.sigma[3] = np.array([[1.0, 2.0], [2.0, 1.0]])
     ctx = solver.Context(None)
     _expect(_lib.PDG_EINVAL, ctx.set_mesh, pr.mesh, 1)
+
+
+def _small_batch():
+    """Three independent 3-D problems of one degree (different meshes, sizes,
+    partitions) concatenated into one batch problem."""
+    systems = [problems.small3d(n_grid=g, p=2, n_sub=ns, seed=sd) for g, ns, sd in ((5, 3, 21), (6, 4, 22), (4, 2, 23))]
+    return systems, problems.concat_problems("batch", systems)
+
+
+def test_batch_host_setup_is_block_diagonal():
+    """A batch context holds exactly the matrices, local inverses and coarse
+    operators of its systems' own contexts (block diagonal over systems)."""
+    systems, bp = _small_batch()
+    cb = solver.from_problem(bp, device=None)
+    row_ptr, col, val, _ = cb.get_matrix()
+    Kb = _dense_from_bsr(row_ptr, col, val, bp.n_elem, bp.nd)
+    Pb, K0b = cb.get_coarse()
+    e0, s0, c0 = 0, 0, 0
+    for q in systems:
+        cq = solver.from_problem(q, device=None)
+        rp, cl, vl, _ = cq.get_matrix()
+        Kq = _dense_from_bsr(rp, cl, vl, q.n_elem, q.nd)
+        d0, d1 = e0 * bp.nd, (e0 + q.n_elem) * bp.nd
+        assert np.array_equal(Kb[d0:d1, d0:d1], Kq)
+        assert not np.any(Kb[d0:d1, :d0]) and not np.any(Kb[d0:d1, d1:])
+        for s in range(q.n_sub):
+            assert np.array_equal(cb.get_local_inverse(s0 + s), cq.get_local_inverse(s))
+        Pq, K0q = cq.get_coarse()
+        assert np.array_equal(Pb[e0:e0 + q.n_elem], Pq)
+        nq = K0q.shape[0]
+        assert np.allclose(K0b[c0:c0 + nq, c0:c0 + nq], K0q, rtol=0, atol=1e-12 * abs(K0q).max())
+        assert not np.any(K0b[c0:c0 + nq, :c0]) and not np.any(K0b[c0:c0 + nq, c0 + nq:])
+        e0 += q.n_elem
+        s0 += q.n_sub
+        c0 += nq
+
+
+def test_batch_validation_errors():
+    systems, bp = _small_batch()
+    ctx = solver.Context(None)
+    ctx.set_mesh(bp.mesh, bp.p)
+    n = bp.n_elem
+    for bad in ([0, n + 1], [1, n], [0, 10, 10, n]):
+        with pytest.raises(PdgError) as e:
+            ctx.set_systems(bad)
+        assert e.value.status == _lib.PDG_EINVAL
+    # a cut through one system leaves facets between the two parts
+    with pytest.raises(PdgError) as e:
+        ctx.set_systems([0, systems[0].n_elem // 2, n])
+    assert e.value.status == _lib.PDG_EINVAL
+    # a subdomain spanning two systems
+    ctx.set_systems(bp.elem_ptr)
+    ctx.assemble(bp.chi_m, bp.c_m, bp.dt, bp.eta0)
+    sub = bp.elem_sub.copy()
+    sub[systems[0].n_elem] = sub[0]
+    with pytest.raises(PdgError) as e:
+        ctx.setup_preconditioner(sub, None, 1)
+    assert e.value.status == _lib.PDG_EINVAL
+    # after setup the system split is fixed
+    ctx.setup_preconditioner(bp.elem_sub, bp.elem_coarse, 1)
+    with pytest.raises(PdgError) as e:
+        ctx.set_systems(bp.elem_ptr)
+    assert e.value.status == _lib.PDG_ESTATE
+
+
+def test_concat_meshes_keeps_systems_apart():
+    systems, bp = _small_batch()
+    m = bp.mesh
+    f = m.facet_elem
+    sys_of = np.searchsorted(bp.elem_ptr, np.arange(m.n_elem), side="right") - 1
+    inner = f[:, 1] >= 0
+    assert np.array_equal(sys_of[f[inner, 0]], sys_of[f[inner, 1]])
+    assert m.n_facet == sum(q.mesh.n_facet for q in systems)
+    assert np.allclose(m.element_measure(), np.concatenate([q.mesh.element_measure() for q in systems]))

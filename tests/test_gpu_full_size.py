@@ -7,6 +7,11 @@
   so properties that hold at any size: with FP32 Schwarz solves the FP64 true
   relative residual still meets 1e-10, and the solution agrees with the FP64
   Schwarz solution of the same step (both meet the same residual) to 1e-8.
+* cfg4 (64 systems, ~1.05M dofs, p = 1..4, one context per degree, graphs on,
+  as benchmarked): every system converges with a true relative residual below
+  2e-10; one system of each degree gives in its own context the same bits and
+  iteration count; the two smallest systems agree with the FP64 oracle (which
+  uses FP64 Schwarz solves) to 1e-8.
 """
 import numpy as np
 import pytest
@@ -93,4 +98,47 @@ def test_cfg3_fp32_schwarz_meets_fp64_tolerance():
         info = c64.step(u0, up0, y0, None, pr.tol, pr.maxit)
         err = rel_l2(N(u32), N(u0))
         print(f"[cfg3] f64 step {k}: iters {info['iters']}; f32 vs f64 rel L2 {err:.2e}", flush=True)
+        assert err < 1e-8
+
+
+@pytest.mark.timeout(600)
+def test_cfg4_batch_full_size():
+    batch = problems.cfg4()
+    print(f"[cfg4] {len(batch.systems)} systems, {batch.n_dof} dofs; setup", flush=True)
+    opts = {_lib.PDG_OPT_GRAPH: 1, _lib.PDG_OPT_TRUE_RESIDUAL: 1}
+    bs = solver.BatchSolver(batch, device=DEV, options=opts)
+    U, Up, Y = bs.initial_state()
+    U0 = [u.clone() for u in U]
+    bs.step(U, Up, Y, 1e-10, 5000)
+    worst = 0.0
+    for i in range(len(batch.systems)):
+        si = bs.system_info(i)
+        assert si["status"] == _lib.PDG_OK
+        worst = max(worst, si["true_relres"])
+    print(f"[cfg4] step 0: worst true relres {worst:.2e}", flush=True)
+    assert worst < 2e-10
+    # one system of each degree in its own context
+    for p, (_, idx) in sorted(batch.groups.items()):
+        i = idx[len(idx) // 2]
+        q = batch.systems[i]
+        c1 = solver.from_problem(q, device=DEV)
+        u, up, y = solver.initial_state(c1, q)
+        info = c1.step(u, up, y, None, q.tol, q.maxit)
+        ci, sl = bs.system_slice(i)
+        print(f"[cfg4] system {i} (p={p}, {q.n_dof} dofs): iters batch {bs.system_info(i)['iters']} "
+              f"single {info['iters']}", flush=True)
+        assert info["iters"] == bs.system_info(i)["iters"]
+        assert np.array_equal(N(u), N(U[ci])[sl])
+        del c1
+    # the two smallest systems against the oracle
+    from oracle.monodomain import Monodomain
+    for i in np.argsort([q.n_dof for q in batch.systems])[:2]:
+        q = batch.systems[int(i)]
+        md = Monodomain(q)
+        Uo, Upo, Yo = md.initial_state()
+        Uo, Upo, Yo, oinfo = md.step(Uo, Upo, Yo)
+        ci, sl = bs.system_slice(int(i))
+        err = rel_l2(N(U[ci])[sl], Uo)
+        print(f"[cfg4] system {int(i)} vs oracle: iters gpu {bs.system_info(int(i))['iters']} "
+              f"oracle {oinfo.iters}, rel L2 {err:.2e}", flush=True)
         assert err < 1e-8
