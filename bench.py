@@ -207,12 +207,116 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args):
+    """Learned initial guess on the cfg2 mesh: 20 training trajectories x 100
+    steps generated by the method, training on the GPU, 5 held-out trajectories
+    x 100 steps evaluated against plain PCG from U^k and against linear
+    extrapolation.  The timed steps are the held-out learned-guess steps
+    (features, inference, guess choice and PCG)."""
+    import numpy as np
+    import torch
+
+    from paper_2512_19536_amd import learned
+    from pdg_inputs import problems
+
+    t0 = time.perf_counter()
+    train_p, test_p = problems.cfg5(n_steps=args.traj_steps)
+    if args.train_trajs:
+        train_p = train_p[:args.train_trajs]
+    if args.test_trajs:
+        test_p = test_p[:args.test_trajs]
+    pr0 = test_p[0]
+    log(f"[bench] workload cfg5: {len(train_p)} training + {len(test_p)} held-out trajectories x "
+        f"{args.traj_steps} steps on {pr0.n_elem} elements, {pr0.n_dof} dofs; inputs {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    trajs = [learned.generate(q, args.traj_steps, log=log) for q in train_p]
+    t_gen = time.perf_counter() - t0
+    n_elem, nd = pr0.n_elem, pr0.nd
+    blk = learned.row_block(n_elem)
+    net = learned.Mlp(nd=nd, max_rows=args.batch_steps * blk)
+    learned.fit_normalisation(net, trajs, n_samples=64, seed=0)
+    net.init_params(0)
+    hist, t_train = learned.train(net, trajs, epochs=args.epochs, batch_steps=args.batch_steps, lr=args.lr, seed=0,
+                                  log=log)
+    # matrix-core throughput of training: timed train steps on a fixed batch
+    rows, n_valid = learned.load_batch(net, trajs, [(0, k) for k in range(args.batch_steps)])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        net.train_step(rows, n_valid, 1e-12)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_train_step = ev0.elapsed_time(ev1) / reps
+    W = learned.WIDTH
+    macs = learned.N_IN * W + 2 * W * W + W * learned.N_OUT
+    flops = rows * 2 * (2 * macs + (2 * W * W + W * learned.N_OUT))
+    tflops = flops / (ms_train_step * 1e-3) / 1e12
+    log(f"[bench] training: {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}; train step {ms_train_step:.3f} ms "
+        f"({rows} rows, {tflops:.1f} TFLOP/s BF16)")
+    recs = [learned.evaluate(net, q, args.traj_steps, log=log) for q in test_p]
+    cat = {k: np.concatenate([r[k] for r in recs]) for k in recs[0]}
+    ms = {k: float(np.mean(cat["t_" + k])) for k in ("plain", "extrap", "learned")}
+    it = {k: float(np.mean(cat[k])) for k in ("plain", "extrap", "learned")}
+    used = float(np.mean(np.asarray(cat["used"]) > 0))
+    log(f"[bench] held-out {len(cat['plain'])} steps: iters plain {it['plain']:.2f} extrap {it['extrap']:.2f} "
+        f"learned {it['learned']:.2f}; ms/step plain {ms['plain']:.3f} extrap {ms['extrap']:.3f} learned "
+        f"{ms['learned']:.3f}; guess used {used:.2f}; max rel diff {float(np.max(cat['diff'])):.1e}")
+    out = {
+        "metric": METRIC,
+        "value": round(pr0.n_dof / (ms["learned"] * 1e-3) / 1e6, 3),
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": int(len(cat["plain"])),
+        "warmup": 0,
+        "ms_per_step": round(ms["learned"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32-schwarz+bf16-mlp",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"cfg5: learned initial guess on the cfg2 mesh ({pr0.n_dof} dofs, p=2, 64 subdomains, "
+                         f"FP32 Schwarz), {len(train_p)}x{args.traj_steps} training steps, "
+                         f"{len(test_p)}x{args.traj_steps} held-out steps, MLP 96-256-256-256-32 BF16"),
+            "n_dof": pr0.n_dof,
+        },
+        "learned": {
+            "iters_mean": it, "ms_per_step": ms,
+            "iteration_reduction_vs_plain": round(1.0 - it["learned"] / it["plain"], 4),
+            "iteration_reduction_vs_extrap": round(1.0 - it["learned"] / it["extrap"], 4),
+            "guess_used_fraction": used, "max_rel_diff_vs_plain": float(np.max(cat["diff"])),
+            "training": {"epochs": args.epochs, "seconds": round(t_train, 2), "loss_first": hist[0],
+                         "loss_last": hist[-1], "data_generation_s": round(t_gen, 1),
+                         "train_step_ms": round(ms_train_step, 4), "rows_per_step": rows},
+        },
+        "roofline": {
+            "kernel": "k_gemm_nt (BF16 MFMA layer products of one training step)",
+            "bound": "mfma",
+            "achieved": round(tflops, 2),
+            "peak": 2500.0,
+            "unit": "TFLOP/s",
+            "frac": round(tflops / 2500.0, 5),
+            "traffic": None,
+        },
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--epochs", type=int, default=30, help="cfg5: training epochs")
+    ap.add_argument("--batch-steps", type=int, default=4, help="cfg5: time steps per training batch")
+    ap.add_argument("--lr", type=float, default=1e-3, help="cfg5: peak learning rate")
+    ap.add_argument("--traj-steps", type=int, default=100, help="cfg5: steps per trajectory")
+    ap.add_argument("--train-trajs", type=int, default=0, help="cfg5: use only the first N training trajectories")
+    ap.add_argument("--test-trajs", type=int, default=0, help="cfg5: use only the first N held-out trajectories")
     ap.add_argument("--graph", type=int, default=None, help="replay PCG chunks as captured graphs (0/1)")
     ap.add_argument("--chunk", type=int, default=4, help="PCG iterations between host polls")
     ap.add_argument("--autotune", action="store_true")
@@ -231,6 +335,8 @@ def main():
         if args.graph is None:
             args.graph = 1
         return bench_batch(args)
+    if args.workload == "cfg5":
+        return bench_learned(args)
     if args.graph is None:
         args.graph = 0
 

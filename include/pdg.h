@@ -63,6 +63,8 @@ typedef struct {
     double relres;        /* ||r_k|| / ||b|| of the recurrence residual            */
     double true_relres;   /* ||b - K x|| / ||b|| if requested, else -1             */
     double bnorm;         /* ||b||                                                 */
+    int32_t guess_used;   /* pdg_step_guess: systems that started from the guess
+                             (0 = all fell back to U^k); -1 = no guess offered      */
 } pdg_solve_info;
 
 /* Create a context on HIP device `hip_device`, launching on `hip_stream`
@@ -262,6 +264,21 @@ pdg_status pdg_solve(pdg_ctx *ctx, const double *rhs, double *x, double tol, int
 pdg_status pdg_step(pdg_ctx *ctx, double *u, double *u_prev, double *ions, const double *f_ext,
                     double tol, int32_t maxit, pdg_solve_info *info);
 
+/* pdg_step with an offered initial guess (the learned form; not part of the
+ * paper): `guess` (device, [n_elem][nd], not aliasing u or u_prev) replaces
+ * x0 = U^k for every system where ||b - K guess|| < ||b - K U^k|| (computed
+ * on the device after b is built); elsewhere the step falls back to x0 = U^k.
+ * The solution meets the same stopping rule either way.  info->guess_used
+ * counts the systems that used the guess.  Synchronises the stream. */
+pdg_status pdg_step_guess(pdg_ctx *ctx, double *u, double *u_prev, double *ions, const double *f_ext,
+                          const double *guess, double tol, int32_t maxit, pdg_solve_info *info);
+
+/* Polynomial extrapolation of the last iterates, a non-learned initial guess:
+ * order 1: guess = 2 u - u1; order 2: guess = 3 u - 3 u1 + u2 (device
+ * vectors, [n_elem][nd]; u2 may be NULL for order 1). */
+pdg_status pdg_guess_extrapolate(pdg_ctx *ctx, const double *u, const double *u1, const double *u2,
+                                 int32_t order, double *guess);
+
 /* For a context holding a batch (pdg_set_systems) the info of pdg_solve /
  * pdg_step summarises all systems: the largest iteration count and relative
  * residuals, and bnorm over all systems; the call returns the first non-OK
@@ -281,6 +298,86 @@ pdg_status pdg_step_batch(pdg_ctx *const *ctxs, int32_t n_ctx, double *const *u,
                           double *const *u_prev, double *const *ions,
                           const double *const *f_ext, double tol, int32_t maxit,
                           pdg_solve_info *info);
+
+/* ------------------------------------------------------------------------
+ * 5. Learned initial guess (the learned form; not part of the paper).
+ * A per-element multilayer perceptron n_in -> width -> width -> width ->
+ * n_out with ReLU between layers predicts, from an element's last four
+ * potentials and its ionic state, the element's update U^(k+1) - U^k; the
+ * prediction is offered to pdg_step_guess, which falls back to U^k wherever it
+ * does not lower the initial residual.  Parameters are FP32 masters with BF16
+ * copies; every layer product runs on the matrix cores in BF16 with FP32
+ * accumulation, in training (forward, backward, Adam) and in inference.
+ *
+ * Parameter vector (FP32, n_params entries), per layer l = 1..4 in order:
+ * W_l [N_l][K_l] row-major, then b_l [N_l]; (K_l, N_l) = (n_in, width),
+ * (width, width), (width, width), (width, n_out).
+ *
+ * Features of element e (9 nd values, then zeros up to n_in), each group of
+ * nd modal coefficients: u^k, u^k - u^(k-1), u^(k-1) - u^(k-2),
+ * u^(k-2) - u^(k-3), then the five ionic states y^k; normalised as
+ * (value - x_shift[f]) * x_scale[f].  Targets: (U^(k+1) - U^k)[e][i] for
+ * i < nd, normalised as (value - t_shift[i]) * t_scale[i]; the loss is the mean
+ * of the squared normalised errors over the rows of weight 1 and the first
+ * n_out_valid outputs.  Rows (samples) are elements; a batch of rows holds
+ * blocks of elements (one block per time step), each padded to a multiple of
+ * 32 with rows of weight 0. */
+typedef struct pdg_mlp pdg_mlp;
+typedef struct {
+    int32_t n_in;         /* multiple of 32, >= 9 nd */
+    int32_t width;        /* multiple of 32 */
+    int32_t n_out;        /* multiple of 32 */
+    int32_t n_out_valid;  /* outputs that carry targets (nd), 1..n_out */
+    int64_t max_rows;     /* rows per batch, multiple of 32 */
+} pdg_mlp_desc;
+
+/* Create on HIP device `hip_device`, launching on `hip_stream` (NULL = default
+ * stream).  Errors: PDG_EINVAL for sizes outside the stated ranges. */
+pdg_status pdg_mlp_create(pdg_mlp **out, int32_t hip_device, void *hip_stream, const pdg_mlp_desc *desc);
+void pdg_mlp_destroy(pdg_mlp *mlp);
+const char *pdg_mlp_last_error(const pdg_mlp *mlp);
+/* n_params, and the bytes of the workspace to bind (256-byte aligned, owned by
+ * the caller, kept alive until pdg_mlp_destroy). */
+pdg_status pdg_mlp_get_sizes(pdg_mlp *mlp, int64_t *n_params, size_t *workspace_bytes);
+pdg_status pdg_mlp_bind_workspace(pdg_mlp *mlp, void *dev_ptr, size_t bytes);
+/* Host parameter vector in / out (n = n_params).  Setting resets Adam. */
+pdg_status pdg_mlp_set_params(pdg_mlp *mlp, const float *params, int64_t n);
+pdg_status pdg_mlp_get_params(pdg_mlp *mlp, float *params, int64_t n);
+/* Normalisation (host arrays: n_in feature shifts and scales, n_out target
+ * shifts and scales; scales > 0). */
+pdg_status pdg_mlp_set_normalisation(pdg_mlp *mlp, const float *x_shift, const float *x_scale,
+                                     const float *t_shift, const float *t_scale);
+/* A batch from the host: X [rows][n_in] BF16 bit patterns (already
+ * normalised), T [rows][n_out] and row weights w [rows] (FP32). */
+pdg_status pdg_mlp_set_batch(pdg_mlp *mlp, int64_t rows, const uint16_t *X, const float *T,
+                             const float *w);
+/* Features of n_elem elements (device vectors [n_elem][nd]: u0 = u^k,
+ * u1 = u^(k-1), u2, u3; ions [5][n_elem][nd]) into batch rows
+ * row0 .. row0 + n_rows (rows past n_elem are zero).  With raw != NULL the
+ * unnormalised values go to raw (device, [n_elem][n_in] FP32) instead. */
+pdg_status pdg_mlp_features(pdg_mlp *mlp, int64_t row0, int64_t n_elem, int64_t n_rows, int32_t nd,
+                            const double *u0, const double *u1, const double *u2, const double *u3,
+                            const double *ions, float *raw);
+/* Targets from u_next = U^(k+1) and u0 = U^k into rows row0 .. row0 + n_rows
+ * (weights 1 for the n_elem element rows, 0 for padding); raw: device
+ * [n_elem][nd] FP32 unnormalised values instead. */
+pdg_status pdg_mlp_targets(pdg_mlp *mlp, int64_t row0, int64_t n_elem, int64_t n_rows, int32_t nd,
+                           const double *u_next, const double *u0, float *raw);
+/* Forward pass over batch rows 0 .. rows (multiple of 32); y_out (device,
+ * [rows][n_out] FP32, normalised units) may be NULL. */
+pdg_status pdg_mlp_forward(pdg_mlp *mlp, int64_t rows, float *y_out);
+/* guess[e][i] = u0[e][i] + de-normalised prediction of batch row row0 + e
+ * (after pdg_mlp_forward). */
+pdg_status pdg_mlp_guess(pdg_mlp *mlp, int64_t row0, int64_t n_elem, int32_t nd, const double *u0,
+                         double *guess);
+/* Forward and backward over batch rows 0 .. rows; n_valid = rows of weight 1
+ * (the loss divides by n_valid * n_out_valid).  grad: host [n_params] or NULL;
+ * loss: host or NULL.  Synchronises. */
+pdg_status pdg_mlp_gradients(pdg_mlp *mlp, int64_t rows, int64_t n_valid, float *grad, double *loss);
+/* One Adam step (bias-corrected) on those gradients.  loss: host or NULL (no
+ * synchronisation when NULL). */
+pdg_status pdg_mlp_train_step(pdg_mlp *mlp, int64_t rows, int64_t n_valid, float lr, float beta1,
+                              float beta2, float eps, double *loss);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,8 @@ Modules (each function cites the passage of the paper it follows):
 * :mod:`oracle.schwarz`     -- two-level additive Schwarz preconditioner (eq. (5)).
 * :mod:`oracle.pcg`         -- PCG and the Lanczos condition-number estimate (Section 5).
 * :mod:`oracle.monodomain`  -- one fully discrete time step (eq. (4)).
+* :mod:`oracle.mlp`         -- the learned initial guess's network (not in the
+                               paper): forward, backward, Adam, BF16 rounding.
 
 Parity status of each function is stated in its module header.
 """

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdg.so")
@@ -28,7 +28,11 @@ EXPORTS = (
     "pdg_assemble", "pdg_get_matrix", "pdg_set_ionic", "pdg_setup_preconditioner", "pdg_get_precond_sizes",
     "pdg_get_local_inverse", "pdg_get_coarse", "pdg_workspace_query", "pdg_bind_workspace", "pdg_set_option",
     "pdg_kernel_timing", "pdg_project_p0", "pdg_spmv", "pdg_precond_apply", "pdg_ionic", "pdg_rhs",
-    "pdg_solve", "pdg_step", "pdg_get_system_info", "pdg_step_batch", "pdg_autotune",
+    "pdg_solve", "pdg_step", "pdg_get_system_info", "pdg_step_batch", "pdg_autotune", "pdg_step_guess",
+    "pdg_guess_extrapolate", "pdg_mlp_create", "pdg_mlp_destroy", "pdg_mlp_last_error", "pdg_mlp_get_sizes",
+    "pdg_mlp_bind_workspace", "pdg_mlp_set_params", "pdg_mlp_get_params", "pdg_mlp_set_normalisation",
+    "pdg_mlp_set_batch", "pdg_mlp_features", "pdg_mlp_targets", "pdg_mlp_forward", "pdg_mlp_guess",
+    "pdg_mlp_gradients", "pdg_mlp_train_step",
 )
 
 
@@ -44,10 +48,17 @@ class PdgPrecondDesc(ctypes.Structure):
 
 
 class PdgSolveInfo(ctypes.Structure):
-    _fields_ = [("iters", c_int32), ("relres", c_double), ("true_relres", c_double), ("bnorm", c_double)]
+    _fields_ = [("iters", c_int32), ("relres", c_double), ("true_relres", c_double), ("bnorm", c_double),
+                ("guess_used", c_int32)]
 
     def as_dict(self):
-        return {"iters": self.iters, "relres": self.relres, "true_relres": self.true_relres, "bnorm": self.bnorm}
+        return {"iters": self.iters, "relres": self.relres, "true_relres": self.true_relres, "bnorm": self.bnorm,
+                "guess_used": self.guess_used}
+
+
+class PdgMlpDesc(ctypes.Structure):
+    _fields_ = [("n_in", c_int32), ("width", c_int32), ("n_out", c_int32), ("n_out_valid", c_int32),
+                ("max_rows", c_int64)]
 
 
 class PdgTuneResult(ctypes.Structure):
@@ -105,6 +116,23 @@ def load():
         "pdg_get_system_info": (I32, [V, I32, POINTER(PdgSolveInfo), POINTER(I32)]),
         "pdg_step_batch": (I32, [P, I32, P, P, P, P, D, I32, P]),
         "pdg_autotune": (I32, [V, I32, POINTER(PdgTuneResult)]),
+        "pdg_step_guess": (I32, [V, P, P, P, P, P, D, I32, POINTER(PdgSolveInfo)]),
+        "pdg_guess_extrapolate": (I32, [V, P, P, P, I32, P]),
+        "pdg_mlp_create": (I32, [POINTER(c_void_p), I32, V, POINTER(PdgMlpDesc)]),
+        "pdg_mlp_destroy": (None, [V]),
+        "pdg_mlp_last_error": (c_char_p, [V]),
+        "pdg_mlp_get_sizes": (I32, [V, POINTER(I64), POINTER(c_size_t)]),
+        "pdg_mlp_bind_workspace": (I32, [V, P, c_size_t]),
+        "pdg_mlp_set_params": (I32, [V, P, I64]),
+        "pdg_mlp_get_params": (I32, [V, P, I64]),
+        "pdg_mlp_set_normalisation": (I32, [V, P, P, P, P]),
+        "pdg_mlp_set_batch": (I32, [V, I64, P, P, P]),
+        "pdg_mlp_features": (I32, [V, I64, I64, I64, I32, P, P, P, P, P, P]),
+        "pdg_mlp_targets": (I32, [V, I64, I64, I64, I32, P, P, P]),
+        "pdg_mlp_forward": (I32, [V, I64, P]),
+        "pdg_mlp_guess": (I32, [V, I64, I64, I32, P, P]),
+        "pdg_mlp_gradients": (I32, [V, I64, I64, P, POINTER(D)]),
+        "pdg_mlp_train_step": (I32, [V, I64, I64, c_float, c_float, c_float, c_float, POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -121,4 +149,10 @@ def status_string(status):
 def check(ctx, status):
     if status != PDG_OK:
         msg = load().pdg_last_error(ctx).decode() if ctx else ""
+        raise PdgError(status, msg)
+
+
+def check_mlp(mlp, status):
+    if status != PDG_OK:
+        msg = load().pdg_mlp_last_error(mlp).decode() if mlp else ""
         raise PdgError(status, msg)

@@ -23,6 +23,8 @@ HOST_ONLY = ["-mavx2", "-mfma", "-I/opt/rocm/include"]
 
 SOURCES = [
     ("kernels.hip", "device"),
+    ("mlp.hip", "device"),
+    ("mlp_api.cpp", "host"),
     ("fem.cpp", "host"),
     ("schwarz_setup.cpp", "host"),
     ("api.cpp", "host"),

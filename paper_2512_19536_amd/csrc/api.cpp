@@ -612,7 +612,7 @@ void ensure_graph(pdg_ctx *c) {
 // z0 = B r0, p0 = z0.  step_mode: b is built from x (= U^k) and the ion term,
 // and u_prev receives U^k.  Enqueue only.
 void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u_prev, const double *f_ext,
-               double tol, int maxit) {
+               double tol, int maxit, const double *guess = nullptr) {
     if (maxit < 0) throw Error(PDG_EINVAL, "maxit < 0");
     if (!(tol >= 0.0)) throw Error(PDG_EINVAL, "tol must be >= 0");
     hipStream_t s = c->stream;
@@ -624,7 +624,44 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
     a.sc = sc;
     a.xcopy = vec(c, c->w.x);
     a.y = vec(c, c->w.r);
-    if (step_mode) {
+    if (step_mode && guess) {
+        // b, then the residuals of u and of the guess; each system starts from
+        // the one with the smaller residual norm
+        SpmvArgs rb = a;
+        rb.mode = SPMV_RHS;
+        rb.y = vec(c, c->w.b);
+        rb.xcopy = nullptr;
+        rb.I = vec(c, c->w.I);
+        rb.f = f_ext;
+        rb.two_c = 2.0 * c->c;
+        rb.chi = c->chi;
+        HIPCHK(launch_spmv(c->dA, rb, s));
+        a.mode = SPMV_RESID;
+        a.b = vec(c, c->w.b);
+        a.u_prev = u_prev;
+        HIPCHK(launch_spmv(c->dA, a, s));
+        HIPCHK(launch_sum_partials(a.part, wptr<int32_t>(c, c->w.rspmv), c->n_sys, 1, sc, s));
+        SpmvArgs ag = a;
+        ag.x = guess;
+        ag.y = vec(c, c->w.t);
+        ag.xcopy = nullptr;
+        ag.u_prev = nullptr;
+        HIPCHK(launch_spmv(c->dA, ag, s));
+        ChooseArgs ch{};
+        ch.nd = c->mesh.nd;
+        ch.grp_ptr = wptr<int32_t>(c, c->w.grpptr);
+        ch.grp_elems = wptr<int32_t>(c, c->w.grpel);
+        ch.grp_sys = wptr<int32_t>(c, c->w.upsys);
+        ch.n_grp = (int)c->grp_ptr.size() - 1;
+        ch.part = a.part;
+        ch.g = guess;
+        ch.r_g = vec(c, c->w.t);
+        ch.x = vec(c, c->w.x);
+        ch.r = vec(c, c->w.r);
+        ch.rng = ranges(c);
+        ch.sc = sc;
+        HIPCHK(launch_choose(ch, s));
+    } else if (step_mode) {
         a.mode = SPMV_STEP;
         a.I = vec(c, c->w.I);
         a.f = f_ext;
@@ -637,11 +674,12 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
         rb.y = vec(c, c->w.b);
         rb.xcopy = nullptr;
         if (c->true_resid) HIPCHK(launch_spmv(c->dA, rb, s));
+        HIPCHK(launch_spmv(c->dA, a, s));
     } else {
         a.mode = SPMV_RESID;
         a.b = b;
+        HIPCHK(launch_spmv(c->dA, a, s));
     }
-    HIPCHK(launch_spmv(c->dA, a, s));
     HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.x), vec(c, c->w.r), sc), s));
     c->ev_used = 0;
     launch_schwarz_timed(c, schwarz_args(c, 1, vec(c, c->w.r), sc));
@@ -716,6 +754,9 @@ pdg_status pcg_end(pdg_ctx *c, pdg_solve_info *info, int *bad_sys) {
             if (c->last[b].bb > 0) c->last_true[b] = std::sqrt(c->sc_host[b].tr / c->last[b].bb);
     }
     pdg_solve_info out{};
+    out.guess_used = -1;
+    for (const DevScalars &h : c->last)
+        if (h.guess >= 0) out.guess_used = std::max(out.guess_used, 0) + h.guess;
     double bb = 0.0;
     out.true_relres = c->true_resid ? 0.0 : -1.0;
     pdg_status st = PDG_OK;
@@ -739,8 +780,8 @@ pdg_status pcg_end(pdg_ctx *c, pdg_solve_info *info, int *bad_sys) {
 }
 
 pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u_prev, const double *f_ext,
-                   double tol, int maxit, pdg_solve_info *info, int *bad_sys) {
-    pcg_begin(c, x, b, step_mode, u_prev, f_ext, tol, maxit);
+                   double tol, int maxit, pdg_solve_info *info, int *bad_sys, const double *guess = nullptr) {
+    pcg_begin(c, x, b, step_mode, u_prev, f_ext, tol, maxit, guess);
     do pcg_launch(c);
     while (!pcg_poll(c));
     return pcg_end(c, info, bad_sys);
@@ -1265,6 +1306,31 @@ pdg_status pdg_step(pdg_ctx *c, double *u, double *u_prev, double *ions, const d
     });
 }
 
+pdg_status pdg_step_guess(pdg_ctx *c, double *u, double *u_prev, double *ions, const double *f_ext,
+                          const double *guess, double tol, int32_t maxit, pdg_solve_info *info) {
+    return guard(c, [&] {
+        require_gpu(c);
+        if (!c->has_ionic) throw Error(PDG_ESTATE, "pdg_set_ionic not called");
+        if (!u || !u_prev || !ions || !guess) throw Error(PDG_EINVAL, "NULL vector");
+        if (guess == u || guess == u_prev) throw Error(PDG_EINVAL, "guess must not alias u or u_prev");
+        launch_ionic_step(c, u, u_prev, ions, vec(c, c->w.I));
+        int bad = -1;
+        const pdg_status st = run_pcg(c, u, nullptr, true, u_prev, f_ext, tol, maxit, info, &bad, guess);
+        if (c->sc_host[0].ionic_bad) throw Error(PDG_ENONFINITE, "ionic: non-positive concentration before a logarithm");
+        if (st != PDG_OK) throw Error(st, pcg_message(st, bad, c->n_sys));
+    });
+}
+
+pdg_status pdg_guess_extrapolate(pdg_ctx *c, const double *u, const double *u1, const double *u2, int32_t order,
+                                 double *guess) {
+    return guard(c, [&] {
+        require_gpu(c);
+        if (order != 1 && order != 2) throw Error(PDG_EINVAL, "order must be 1 or 2");
+        if (!u || !u1 || !guess || (order == 2 && !u2)) throw Error(PDG_EINVAL, "NULL vector");
+        HIPCHK(launch_extrapolate(u, u1, order == 2 ? u2 : u1, order, c->mesh.n_elem * c->mesh.nd, guess, c->stream));
+    });
+}
+
 pdg_status pdg_step_batch(pdg_ctx *const *ctxs, int32_t n_ctx, double *const *u, double *const *u_prev,
                           double *const *ions, const double *const *f_ext, double tol, int32_t maxit,
                           pdg_solve_info *info) {
@@ -1323,6 +1389,7 @@ pdg_status pdg_get_system_info(const pdg_ctx *cc, int32_t sys, pdg_solve_info *i
         if (c->last.empty()) throw Error(PDG_ESTATE, "no solve yet");
         const DevScalars &h = c->last[sys];
         if (info) {
+            info->guess_used = h.guess;
             info->iters = h.iters;
             info->bnorm = std::sqrt(h.bb);
             info->relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;

@@ -27,7 +27,8 @@ struct DevScalars {
     int32_t jcur;       // iteration in progress (set by the update kernel, read by the p-update kernel)
     int32_t maxit;
     int32_t ionic_bad;  // a concentration <= 0 met before a logarithm (system 0 holds the batch flag)
-    int32_t pad[2];
+    int32_t guess;      // -1 no initial guess offered, 0 rejected (x0 = U^k), 1 used
+    int32_t pad;
 };
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_ZERO_RHS = 2, ST_NOCONV = -5, ST_BREAKDOWN = -6, ST_NONFINITE = -7 };
@@ -63,7 +64,7 @@ struct SpmvArgs {
     const double *b;        // RESID: right-hand side
     const double *I;        // STEP/RHS: ion term
     const double *f;        // STEP/RHS: optional applied current (nullable)
-    double *u_prev;         // STEP: receives a copy of x
+    double *u_prev;         // STEP, RESID: receives a copy of x (nullable in RESID)
     double *xcopy;          // STEP/RESID: receives a copy of x (the PCG iterate), nullable
     double two_c, chi;      // STEP/RHS constants
     double *part;           // [groups][2] per-workgroup sums (PQ: (p,q); RESID: ||b||^2, ||r||^2; STEP: ||b||^2)
@@ -170,6 +171,22 @@ hipError_t launch_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
 // Sums the SpMV partials (stride 2, slot `slot`) of each system into sc[s].tr.
 hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_sys, int slot, DevScalars *sc,
                                hipStream_t s);
+// Initial guess choice, per system: where ||b - K g||^2 (SpMV partials, slot 1)
+// is below ||b - K u||^2 (sc.tr), x = g and r = r_g; else x and r stay those of u.
+struct ChooseArgs {
+    int nd;
+    const int32_t *grp_ptr, *grp_elems, *grp_sys;  // update chunks
+    int n_grp;
+    const double *part;      // SpMV partials of the guess residual
+    const double *g, *r_g;   // guess and its residual
+    double *x, *r;           // PCG iterate and residual (hold those of u)
+    SysRanges rng;
+    DevScalars *sc;
+};
+hipError_t launch_choose(const ChooseArgs &a, hipStream_t s);
+// guess = 2 u - u1 (order 1) or 3 u - 3 u1 + u2 (order 2)
+hipError_t launch_extrapolate(const double *u, const double *u1, const double *u2, int order, int64_t n,
+                              double *guess, hipStream_t s);
 // out = x on every dof, except 0 on the dofs of systems that stopped with a zero right-hand side.
 hipError_t launch_finish(const double *x, double *out, const int32_t *elem_sys, int nd, int64_t n_elem,
                          const DevScalars *sc, hipStream_t s);

@@ -139,6 +139,7 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
             const double bv = a.b[idx], rv = bv - acc;
             a.y[idx] = rv;
             if (a.xcopy) a.xcopy[idx] = a.x[idx];
+            if (a.u_prev) a.u_prev[idx] = a.x[idx];
             part[0] = bv * bv;
             part[1] = rv * rv;
             break;
@@ -842,6 +843,32 @@ __global__ void k_finish(const double *x, double *out, const int32_t *elem_sys, 
         out[t] = sc[elem_sys[t / nd]].status == ST_ZERO_RHS ? 0.0 : x[t];
 }
 
+// One block per update chunk (inside one system): the system's guess residual
+// norm from the SpMV partials, compared with that of u, decides the chunk's
+// dofs; the system's first chunk records the decision.
+__global__ __launch_bounds__(128) void k_choose(ChooseArgs a) {
+    const int c = blockIdx.x, b = a.grp_sys[c];
+    DevScalars *sc = a.sc + b;
+    const int g0 = a.rng.spmv[b];
+    const double rg = block_sum_partials<128>(a.part + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 1);
+    const bool use = rg < sc->tr;
+    if (c == a.rng.upd[b] && threadIdx.x == 0) sc->guess = use ? 1 : 0;
+    if (!use) return;
+    const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * a.nd;
+    for (int d = threadIdx.x; d < ndof; d += 128) {
+        const int le = d / a.nd, i = d - le * a.nd;
+        const int64_t idx = (int64_t)a.grp_elems[e0 + le] * a.nd + i;
+        a.x[idx] = a.g[idx];
+        a.r[idx] = a.r_g[idx];
+    }
+}
+
+__global__ void k_extrapolate(const double *u, const double *u1, const double *u2, int order, int64_t n,
+                              double *guess) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        guess[t] = order == 1 ? 2.0 * u[t] - u1[t] : 3.0 * (u[t] - u1[t]) + u2[t];
+}
+
 __global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit, int reset_ionic) {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_sys; b += gridDim.x * blockDim.x) {
         DevScalars &d = sc[b];
@@ -853,6 +880,7 @@ __global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
         d.status = ST_RUN;
         d.iters = 0;
         d.jcur = 0;
+        d.guess = -1;
         d.maxit = maxit;
     }
 }
@@ -1023,6 +1051,18 @@ hipError_t launch_project_p0(const double *vals, int ncomp, int64_t n_elem, int 
 hipError_t launch_finish(const double *x, double *out, const int32_t *elem_sys, int nd, int64_t n_elem,
                          const DevScalars *sc, hipStream_t s) {
     hipLaunchKernelGGL(k_finish, dim3(grid_for(n_elem * nd)), dim3(256), 0, s, x, out, elem_sys, nd, n_elem, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_choose(const ChooseArgs &a, hipStream_t s) {
+    if (a.n_grp <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_choose, dim3(a.n_grp), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(const double *u, const double *u1, const double *u2, int order, int64_t n,
+                              double *guess, hipStream_t s) {
+    hipLaunchKernelGGL(k_extrapolate, dim3(grid_for(n)), dim3(256), 0, s, u, u1, u2, order, n, guess);
     return hipGetLastError();
 }
 

@@ -181,6 +181,16 @@ class Context:
         check(self._ctx, st)
         return info.as_dict()
 
+    def step_guess(self, u, u_prev, ions, f_ext, guess, tol, maxit):
+        info = PdgSolveInfo()
+        st = self.lib.pdg_step_guess(self._ctx, _ptr(u), _ptr(u_prev), _ptr(ions), _ptr(f_ext), _ptr(guess),
+                                     float(tol), int(maxit), ctypes.byref(info))
+        check(self._ctx, st)
+        return info.as_dict()
+
+    def guess_extrapolate(self, u, u1, u2, order, guess):
+        self._call("pdg_guess_extrapolate", _ptr(u), _ptr(u1), _ptr(u2), int(order), _ptr(guess))
+
     def system_info(self, sys):
         info, st = PdgSolveInfo(), ctypes.c_int32()
         self._call("pdg_get_system_info", int(sys), ctypes.byref(info), ctypes.byref(st))

@@ -30,11 +30,17 @@ Workloads
           subdomains of equal target size (so about 250 dofs each) with the P1
           coarse space on them, FP32 Schwarz solves.  Systems of one degree are
           concatenated into one problem (``elem_ptr`` gives the systems).
+``cfg5``  trajectories for the learned initial guess on the cfg2 mesh, partition
+          and time step: trajectory s has a +30 mV stimulus in the ball of
+          radius 1.5 mm around a seeded random centre and, in the white region,
+          conductivity 3 sigma0 along a seeded random fibre field and sigma0
+          across it (grey: sigma0, isotropic); FP32 Schwarz solves.  Training
+          seeds 100..119, held-out seeds 200..204, 100 steps each.
 ``small3d`` a tiny 3-D problem (6^3 cubes) for quick tests.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -207,6 +213,52 @@ def small2d(n=24, p=2, seed=5) -> Problem:
     return Problem(f"small2d_{n}_p{p}", mesh, p=p, chi_m=1.0, c_m=1.0, dt=0.05, eta0=10.0,
                    elem_sub=sub.astype(np.int32), elem_coarse=sub.astype(np.int32), coarse_q=1,
                    n_steps=3, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(ne))
+
+
+def trajectory_problem(base: Problem, seed, radius=None, white_ratio=3.0, prec="f32") -> Problem:
+    """A variant of `base` (same mesh, partition and constants) with a seeded
+    ball stimulus and a seeded fibre field in the white region (region 1)."""
+    rng = np.random.default_rng(seed)
+    mesh = base.mesh
+    cen = mesh.element_centroid()
+    lo, hi = cen.min(0), cen.max(0)
+    if radius is None:
+        radius = 0.15 * float(np.max(hi - lo))
+    sigma0 = float(base.mesh.sigma[:, 0, 0].min())
+    fib = fibre_field(cen, seed)
+    sig = isotropic_sigma(mesh.n_elem, mesh.dim, sigma0)
+    white = np.asarray(mesh.region) == 1
+    sig[white] = fibre_sigma(fib[white], white_ratio * sigma0, sigma0)
+    centre = lo + rng.random(mesh.dim) * (hi - lo)
+    dist = np.linalg.norm(cen - centre, axis=1)
+    inside = dist < radius
+    if not inside.any():
+        inside[np.argmin(dist)] = True
+    u0 = np.full(mesh.n_elem, params.U_REST)
+    u0[inside] += 30.0
+    m2 = replace(mesh, sigma=sig, extra=dict(mesh.extra, fibre=fib))
+    return replace(base, name=f"{base.name}_traj{seed}", mesh=m2, u0_elem=u0,
+                   y0_elem=_rest_state(mesh.n_elem), local_prec=prec, coarse_prec=prec)
+
+
+def learned_small(n_grid=12, p=2, n_sub=8, seed=31) -> Problem:
+    """A small cube (n_grid^3 cubes of 0.25 mm) with the 3-D physics of cfg2,
+    the base of quick trajectory sets for the learned form."""
+    return _cube_problem(f"learned_small_{n_grid}", n_grid, 0.25 * n_grid, seed_mesh=seed, seed_part=seed + 1,
+                         n_sub=n_sub, p=p, spread=0.3, sigma_kind="two_region", n_steps=40,
+                         sigma0=SIGMA_3D, dt=DT_3D)
+
+
+CFG5_TRAIN_SEEDS = tuple(range(100, 120))
+CFG5_TEST_SEEDS = tuple(range(200, 205))
+
+
+def cfg5(n_steps=100):
+    """(training problems, held-out problems) of the learned form on the cfg2 mesh."""
+    base = cfg2()
+    base.n_steps = n_steps
+    return ([trajectory_problem(base, s) for s in CFG5_TRAIN_SEEDS],
+            [trajectory_problem(base, s) for s in CFG5_TEST_SEEDS])
 
 
 def concat_problems(name, probs) -> Problem:
