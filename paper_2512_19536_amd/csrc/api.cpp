@@ -56,7 +56,8 @@ struct Ws {
     int grows, gslot, gcol, gval, gsys, mass, minv, qpptr, qpxi, qpw, norm, prm, subptr, subel;
     int itsys, itrow, itj0, itnj, itown, rtit0, dofrt, itdot, rowpart;
     int sysn, sysnt, systoff, sysdof0, syscb, rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
-    int grpptr, grpel, upsys, cchunk, csys0, crt0, rspmv, rupd, ritem, rowner;
+    int grpptr, grpel, upsys, cchunk, csys0, crt0, csys, rspmv, rupd, ritem, rowner;
+    int spwg, upwg, chunk0;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
 };
 
@@ -94,8 +95,11 @@ struct pdg_ctx {
     int n_sys = 1;
     std::vector<int64_t> sys_elem_ptr;
     std::vector<int32_t> elem_sys;
-    // per-system ranges of the partial producers
+    // per-system ranges of units (groups, chunks, items) and of the producer
+    // workgroups that own runs of them (one partial per workgroup)
+    std::vector<int32_t> r_grp, r_chunk, r_itm;
     std::vector<int32_t> r_spmv, r_upd, r_item, r_owner;
+    std::vector<int32_t> spmv_wg_g0, upd_wg_c0;
     // update chunks (element runs inside one coarse element)
     std::vector<int32_t> grp_ptr, grp_elems, upd_sys, cchunk_ptr;
     // Schwarz work items and tile rows
@@ -103,6 +107,7 @@ struct pdg_ctx {
     std::vector<int64_t> rt_cbase;
     int max_nj = 1;
     int64_t items_reserved = 0;
+    int pre_pq = 0, pre_rz = 0;  // dot products pre-summed by the reduction kernel
     // group-ELL matrix (host staging)
     int G = 1;
     int64_t n_groups = 0, n_slots = 0;
@@ -165,6 +170,33 @@ void drop_graph(pdg_ctx *c) {
     c->gexec_chunk = 0;
 }
 
+// Workgroups of the update kernel per system (about 8 per CU); the SpMV and
+// Schwarz kernels keep one group / item per workgroup (the most loads in flight).
+constexpr int kUpdateTarget = 2048;
+constexpr int kOnePerWorkgroup = 1 << 30;
+// Above this many (consumer workgroup x partial) reads per system, a
+// dedicated reduction kernel sums the partials once instead.
+constexpr int64_t kRedundantReads = 1 << 22;
+
+// Splits each system's unit range [r_unit[s], r_unit[s+1]) into workgroups
+// of per_s = ceil(n_s / target) consecutive units; wg0 receives the first unit
+// of every workgroup (+ end), r_wg the workgroup range of each system.  The
+// split of a system depends on that system alone, so its partial sums (and
+// results) are the same alone or inside a batch.
+void split_units(const std::vector<int32_t> &r_unit, int target, std::vector<int32_t> &wg0,
+                 std::vector<int32_t> &r_wg) {
+    const int n_sys = (int)r_unit.size() - 1;
+    wg0.clear();
+    r_wg.assign(n_sys + 1, 0);
+    for (int b = 0; b < n_sys; ++b) {
+        const int64_t n_b = r_unit[b + 1] - r_unit[b];
+        const int64_t per = std::max<int64_t>(1, (n_b + target - 1) / target);
+        for (int64_t u = r_unit[b]; u < r_unit[b + 1]; u += per) wg0.push_back((int32_t)u);
+        r_wg[b + 1] = (int32_t)wg0.size();
+    }
+    wg0.push_back(r_unit[n_sys]);
+}
+
 // Group-ELL form of K: element rows sorted by (system, neighbour count
 // descending), cut into groups of G rows that never straddle two systems.
 void build_group_ell(pdg_ctx *c) {
@@ -181,16 +213,17 @@ void build_group_ell(pdg_ctx *c) {
     });
     c->grp_rows.clear();
     c->grp_sys.clear();
-    c->r_spmv.assign(c->n_sys + 1, 0);
+    c->r_grp.assign(c->n_sys + 1, 0);
     for (int b = 0; b < c->n_sys; ++b) {
         const int64_t r0 = c->sys_elem_ptr[b], r1 = c->sys_elem_ptr[b + 1];  // rows of b are contiguous in perm
         for (int64_t k = r0; k < r1; k += G) {
             for (int r = 0; r < G; ++r) c->grp_rows.push_back(k + r < r1 ? perm[k + r] : -1);
             c->grp_sys.push_back(b);
         }
-        c->r_spmv[b + 1] = (int32_t)c->grp_sys.size();
+        c->r_grp[b + 1] = (int32_t)c->grp_sys.size();
     }
     c->n_groups = (int64_t)c->grp_sys.size();
+    split_units(c->r_grp, kOnePerWorkgroup, c->spmv_wg_g0, c->r_spmv);
     c->grp_slot_off.assign(c->n_groups + 1, 0);
     for (int64_t g = 0; g < c->n_groups; ++g) {
         int64_t smax = 0;
@@ -228,7 +261,7 @@ void build_group_ell(pdg_ctx *c) {
 // Update chunks: runs of at most 32 elements inside one coarse element (or
 // inside one system without a coarse level), in system order.
 void plan_chunks(pdg_ctx *c) {
-    constexpr int kChunk = 32;
+    const int kChunk = std::max(1, 128 / c->mesh.nd);  // about one dof per thread of the update kernel
     const Precond &pc = c->pc;
     c->grp_ptr.assign(1, 0);
     c->grp_elems.clear();
@@ -253,9 +286,27 @@ void plan_chunks(pdg_ctx *c) {
         for (int b = 0; b < c->n_sys; ++b)
             add_run(&el[c->sys_elem_ptr[b]], c->sys_elem_ptr[b + 1] - c->sys_elem_ptr[b], b);
     }
-    c->r_upd.assign(c->n_sys + 1, 0);
-    for (int32_t b : c->upd_sys) c->r_upd[b + 1]++;
-    for (int b = 0; b < c->n_sys; ++b) c->r_upd[b + 1] += c->r_upd[b];
+    c->r_chunk.assign(c->n_sys + 1, 0);
+    for (int32_t b : c->upd_sys) c->r_chunk[b + 1]++;
+    for (int b = 0; b < c->n_sys; ++b) c->r_chunk[b + 1] += c->r_chunk[b];
+    split_units(c->r_chunk, kUpdateTarget, c->upd_wg_c0, c->r_upd);
+}
+
+// Per system: the update kernel's workgroups each sum the system's SpMV
+// partials, the p-update kernel's workgroups its Schwarz shares; where that
+// is many reads, the reduction kernel does it once.
+void choose_reductions(pdg_ctx *c) {
+    int64_t upd = 0, pup = 0;
+    const int nd = c->mesh.nd;
+    for (int b = 0; b < c->n_sys; ++b) {
+        const int64_t n_up = c->r_upd[b + 1] - c->r_upd[b], n_sp = c->r_spmv[b + 1] - c->r_spmv[b];
+        const int64_t dofs = (c->sys_elem_ptr[b + 1] - c->sys_elem_ptr[b]) * nd;
+        const int64_t n_pu = (dofs + 255) / 256 + 1, n_sw = c->r_item[b + 1] - c->r_item[b];
+        upd = std::max(upd, n_up * n_sp);
+        pup = std::max(pup, n_pu * n_sw);
+    }
+    c->pre_pq = upd > kRedundantReads;
+    c->pre_rz = pup > kRedundantReads;
 }
 
 size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32 ? 4 : 2); }
@@ -277,7 +328,7 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
         c->rt_item0.assign(1, 0);
         c->rt_k.clear(); c->rt_nt.clear(); c->rt_cbase.clear();
         c->coarse_rt0.assign(c->n_sys, 0);
-        c->r_item.assign(c->n_sys + 1, 0);
+        c->r_itm.assign(c->n_sys + 1, 0);
         c->max_nj = 1;
     }
     std::vector<int32_t> rt0_of_sub(pc.n_sub, 0);
@@ -315,9 +366,10 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
             if (!count_only) c->coarse_rt0[b] = n_rt;
             add_sys(pc.n_sub + b, b);
         }
-        if (!count_only) c->r_item[b + 1] = (int32_t)c->it_sys.size();
+        if (!count_only) c->r_itm[b + 1] = (int32_t)c->it_sys.size();
     }
     if (count_only) return count;
+    c->r_item = c->r_itm;  // one Schwarz workgroup (and share of (r, z)) per item
     // tile row (and row inside it) of every fine dof, for assembling z
     c->dof_rt.assign(c->mesh.n_elem * nd, 0);
     for (int s = 0; s < pc.n_sub; ++s) {
@@ -363,7 +415,7 @@ void plan_layout(pdg_ctx *c) {
     w.itown = L.add(n_items * 4);
     w.rtit0 = L.add((n_rt + 1) * 4);
     w.dofrt = L.add(N * 4);
-    w.itdot = L.add(n_items * 8);
+    w.itdot = L.add(n_items * 8);  // one share per Schwarz workgroup (at most one per item)
     w.rowpart = L.add(n_items * kTile * 8);
     w.sysn = L.add(n_dsys * 4);
     w.sysnt = L.add(n_dsys * 4);
@@ -385,10 +437,14 @@ void plan_layout(pdg_ctx *c) {
     w.cchunk = L.add(c->cchunk_ptr.size() * 4);
     w.csys0 = L.add((n_sys + 1) * 4);
     w.crt0 = L.add(n_sys * 4);
+    w.csys = L.add(std::max(pc.n_coarse, 1) * 4);
     w.rspmv = L.add((n_sys + 1) * 4);
     w.rupd = L.add((n_sys + 1) * 4);
     w.ritem = L.add((n_sys + 1) * 4);
     w.rowner = L.add(n_sys * 4);
+    w.spwg = L.add(c->spmv_wg_g0.size() * 4);
+    w.upwg = L.add(c->upd_wg_c0.size() * 4);
+    w.chunk0 = L.add(n_sys * 4);
     w.x = L.add(N * 8);
     w.r = L.add(N * 8);
     w.z = L.add(N * 8);
@@ -400,8 +456,8 @@ void plan_layout(pdg_ctx *c) {
     w.r0p = L.add(std::max<int64_t>(1, n_chunks * std::max(pc.nq0, 1)) * 8);
     w.sc = L.add(n_sys * sizeof(DevScalars));
     w.sca = L.add(n_sys * sizeof(DevScalars));
-    w.part = L.add(std::max<int64_t>(1, c->n_groups) * 2 * 8);  // SpMV partials
-    w.rrpart = L.add(std::max<int64_t>(1, n_chunks) * 8);       // update partials
+    w.part = L.add(std::max<int64_t>(1, (int64_t)c->spmv_wg_g0.size()) * 2 * 8);  // SpMV partials
+    w.rrpart = L.add(std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8);     // update partials
 }
 
 template <class T>
@@ -479,29 +535,26 @@ SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) 
     return a;
 }
 
-void launch_schwarz_plain(pdg_ctx *c, const SchwarzArgs &a) {
+void launch_schwarz_plain(pdg_ctx *c, const SchwarzArgs &a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     HIPCHK(launch_schwarz(a, (int)c->it_sys.size(), store_kind(c->pc.local_prec), store_kind(c->pc.coarse_prec),
-                          c->max_nj, c->stream));
+                          c->max_nj, c->stream, e0, e1));
 }
 
+// With kernel timing on, the launch carries a pair of pool events that the
+// dispatch itself stamps at kernel start and end.
 void launch_schwarz_timed(pdg_ctx *c, const SchwarzArgs &a) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-        if (c->ev_used == c->ev_pool.size()) {
-            hipEvent_t x, y;
-            HIPCHK(hipEventCreate(&x));
-            HIPCHK(hipEventCreate(&y));
-            c->ev_pool.push_back({x, y});
-        }
-        e0 = c->ev_pool[c->ev_used].first;
-        e1 = c->ev_pool[c->ev_used].second;
-        HIPCHK(hipEventRecord(e0, c->stream));
+    if (!c->timing) {
+        launch_schwarz_plain(c, a);
+        return;
     }
-    launch_schwarz_plain(c, a);
-    if (c->timing) {
-        HIPCHK(hipEventRecord(e1, c->stream));
-        c->ev_used++;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t x, y;
+        HIPCHK(hipEventCreate(&x));
+        HIPCHK(hipEventCreate(&y));
+        c->ev_pool.push_back({x, y});
     }
+    launch_schwarz_plain(c, a, c->ev_pool[c->ev_used].first, c->ev_pool[c->ev_used].second);
+    c->ev_used++;
 }
 
 // Collects the timings of the first `keep` recorded Schwarz launches of the
@@ -520,12 +573,14 @@ void harvest_timing(pdg_ctx *c, size_t keep) {
 UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *sc) {
     UpdateArgs u{};
     u.init = init;
+    u.pre_pq = c->pre_pq;
     u.nd = c->mesh.nd;
     u.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
     u.grp_ptr = wptr<int32_t>(c, c->w.grpptr);
     u.grp_elems = wptr<int32_t>(c, c->w.grpel);
     u.grp_sys = wptr<int32_t>(c, c->w.upsys);
-    u.n_grp = (int)c->grp_ptr.size() - 1;
+    u.wg_c0 = wptr<int32_t>(c, c->w.upwg);
+    u.n_wg = (int)c->upd_wg_c0.size() - 1;
     u.x = x;
     u.r = r;
     u.p = wptr<double>(c, c->w.p);
@@ -542,6 +597,7 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
 PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
     PupdateArgs p{};
     p.mode = mode;
+    p.pre_rz = c->pre_rz;
     p.nd = c->mesh.nd;
     p.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
     p.n_elem = c->mesh.n_elem;
@@ -555,6 +611,7 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
     p.rt_cbase = wptr<int64_t>(c, c->w.rtcb);
     p.coarse_rt0 = wptr<int32_t>(c, c->w.crt0);
     p.csys_ce0 = wptr<int32_t>(c, c->w.csys0);
+    p.coarse_sys = wptr<int32_t>(c, c->w.csys);
     p.part = wptr<double>(c, c->w.rowpart);
     p.colpart = wptr<double>(c, c->w.colp);
     p.itemdot = wptr<double>(c, c->w.itdot);
@@ -579,9 +636,12 @@ void launch_iteration(pdg_ctx *c, bool timed) {
     q.part = vec(c, c->w.part);
     q.sc = c->sc;
     HIPCHK(launch_spmv(c->dA, q, s));
+    if (c->pre_pq) HIPCHK(launch_reduce(q.part, wptr<int32_t>(c, c->w.rspmv), c->n_sys, 0, c->sc, s));
     HIPCHK(launch_update(update_args(c, 0, vec(c, c->w.x), vec(c, c->w.r), c->sc), s));
     if (timed) launch_schwarz_timed(c, schwarz_args(c, 2, vec(c, c->w.r), c->sc));
     else launch_schwarz_plain(c, schwarz_args(c, 2, vec(c, c->w.r), c->sc));
+    if (c->pre_rz)
+        HIPCHK(launch_reduce(vec(c, c->w.itdot), wptr<int32_t>(c, c->w.ritem), c->n_sys, 1, c->sc, s));
     HIPCHK(launch_pupdate(pupdate_args(c, 2, vec(c, c->w.p), c->sc), s));
 }
 
@@ -652,6 +712,7 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
         ch.grp_ptr = wptr<int32_t>(c, c->w.grpptr);
         ch.grp_elems = wptr<int32_t>(c, c->w.grpel);
         ch.grp_sys = wptr<int32_t>(c, c->w.upsys);
+        ch.sys_chunk0 = wptr<int32_t>(c, c->w.chunk0);
         ch.n_grp = (int)c->grp_ptr.size() - 1;
         ch.part = a.part;
         ch.g = guess;
@@ -683,6 +744,7 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
     HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.x), vec(c, c->w.r), sc), s));
     c->ev_used = 0;
     launch_schwarz_timed(c, schwarz_args(c, 1, vec(c, c->w.r), sc));
+    if (c->pre_rz) HIPCHK(launch_reduce(vec(c, c->w.itdot), wptr<int32_t>(c, c->w.ritem), c->n_sys, 1, sc, s));
     HIPCHK(launch_pupdate(pupdate_args(c, 1, vec(c, c->w.p), sc), s));
     PcgRun &R = c->run;
     R = PcgRun();
@@ -980,6 +1042,7 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         c->items_reserved = std::max<int64_t>((int64_t)c->it_sys.size(), plan_items(c, std::min(c->item_kb, 64), true));
         c->r_owner.assign(c->n_sys, 0);
         for (int b = 0; b < c->n_sys; ++b) c->r_owner[b] = (int32_t)(c->sys_elem_ptr[b] * c->mesh.nd / 256);
+        choose_reductions(c);
         // algorithmic bytes of one Schwarz apply: stored tiles + input gathers + outputs
         int64_t lt = 0, ctl = 0;
         for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx)
@@ -1093,9 +1156,18 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.rtcb, c->rt_cbase);
         upload(c, w.crt0, c->coarse_rt0);
         upload(c, w.csys0, pc.q > 0 ? pc.csys_ce0 : std::vector<int32_t>(c->n_sys + 1, 0));
+        if (pc.q > 0) {
+            std::vector<int32_t> csys(pc.n_coarse);
+            for (int b = 0; b < c->n_sys; ++b)
+                for (int cc = pc.csys_ce0[b]; cc < pc.csys_ce0[b + 1]; ++cc) csys[cc] = b;
+            upload(c, w.csys, csys);
+        }
         upload(c, w.rspmv, c->r_spmv);
         upload(c, w.rupd, c->r_upd);
         upload(c, w.rowner, c->r_owner);
+        upload(c, w.spwg, c->spmv_wg_g0);
+        upload(c, w.upwg, c->upd_wg_c0);
+        upload(c, w.chunk0, std::vector<int32_t>(c->r_chunk.begin(), c->r_chunk.end() - 1));
         upload(c, w.elsys, c->elem_sys);
         std::vector<int32_t> sys_n, sys_nt;
         std::vector<int64_t> sys_toff, sys_cb;
@@ -1166,6 +1238,8 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         c->dA.grp_val = wptr<double>(c, w.gval);
         c->dA.mass = wptr<double>(c, w.mass);
         c->dA.grp_sys = wptr<int32_t>(c, w.gsys);
+        c->dA.wg_g0 = wptr<int32_t>(c, w.spwg);
+        c->dA.n_wg = (int)c->spmv_wg_g0.size() - 1;
         c->sc = wptr<DevScalars>(c, w.sc);
         c->sc_apply = wptr<DevScalars>(c, w.sca);
         c->state = S_BOUND;
@@ -1445,6 +1519,7 @@ pdg_status pdg_autotune(pdg_ctx *c, int32_t reps, pdg_tune_result *out) {
             plan_items(c, best_kb, false);
             upload_items(c);
             c->item_kb = best_kb;
+            choose_reductions(c);
             res.item_kb = best_kb;
             res.schwarz_us = best * 1e3;
             // SpMV wavefronts per group

@@ -20,6 +20,8 @@ namespace pdg {
 struct DevScalars {
     double bb, rr, pq, alpha, beta, tol2;
     double tr;          // ||b - K x||^2 (true residual, optional)
+    double pq_sum;      // (p, q) summed by the reduction kernel (when the update kernel does not sum it)
+    double rz_sum;      // (r, z) summed by the reduction kernel (when the p-update kernel does not sum it)
     double rz[2];       // (r, z) of the search directions of even / odd index
     int32_t done;       // 1 = this system stops
     int32_t status;     // 0 running, 1 converged, 2 zero rhs, -5 noconv, -6 breakdown, -7 nonfinite
@@ -33,12 +35,13 @@ struct DevScalars {
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_ZERO_RHS = 2, ST_NOCONV = -5, ST_BREAKDOWN = -6, ST_NONFINITE = -7 };
 
-// Per-system ranges of the partial-sum producers: system s owns [x[s], x[s+1]).
+// Per-system ranges of the partial-sum producers (workgroups of the SpMV,
+// update and Schwarz kernels, one partial each): system s owns [x[s], x[s+1]).
 struct SysRanges {
     int n_sys;
-    const int32_t *spmv;    // SpMV workgroups (groups)
-    const int32_t *upd;     // update chunks
-    const int32_t *item;    // Schwarz items
+    const int32_t *spmv;    // SpMV workgroups
+    const int32_t *upd;     // update workgroups
+    const int32_t *item;    // Schwarz workgroups
     const int32_t *owner;   // [n_sys] p-update workgroup holding the system's first dof
 };
 
@@ -53,6 +56,8 @@ struct DevMatrix {
     const double *grp_val;       // [slots*G*nd*nd]
     const double *mass;          // [n_rows][nd][nd]
     const int32_t *grp_sys;      // [n_groups] system of each group
+    const int32_t *wg_g0;        // [n_wg+1] groups of each workgroup (contiguous, one system)
+    int n_wg;
 };
 
 enum SpmvMode { SPMV_PLAIN = 0, SPMV_PQ = 1, SPMV_RESID = 2, SPMV_STEP = 3, SPMV_RHS = 4 };
@@ -73,16 +78,18 @@ struct SpmvArgs {
 
 struct UpdateArgs {
     int init;               // 1: no x/r update (iteration 0)
+    int pre_pq;             // 1: take (p, q) from sc.pq_sum instead of summing the SpMV partials
     int nd, nq0;
     const int32_t *grp_ptr, *grp_elems;  // update chunks: element runs inside one coarse element
     const int32_t *grp_sys;              // system of each chunk
-    int n_grp;
+    const int32_t *wg_c0;                // [n_wg+1] chunks of each workgroup (contiguous, one system)
+    int n_wg;
     double *x, *r;
     const double *p, *q;
     const double *P;        // [n_elem][nd][nq0] or null
     double *r0part;         // [n_grp][nq0] per-chunk restriction, or null
     const double *pqpart;   // SpMV partials ((p, q) in slot 0)
-    double *rrpart;         // [n_grp] per-chunk ||r||^2
+    double *rrpart;         // [n_wg] per-workgroup ||r||^2
     SysRanges rng;
     DevScalars *sc;
 };
@@ -120,6 +127,7 @@ struct SchwarzArgs {
 // iteration: (r, z), beta, convergence on ||r||^2.
 struct PupdateArgs {
     int mode;               // 0: out = z; 1: PCG init, p = z; 2: PCG, p = z + beta p
+    int pre_rz;             // 1: take (r, z) from sc.rz_sum instead of summing the Schwarz shares
     int nd, nq0;
     int64_t n_elem;
     const double *P;
@@ -131,6 +139,7 @@ struct PupdateArgs {
     const int64_t *rt_cbase;     // global tile index of the dense system's first tile
     const int32_t *coarse_rt0;   // [n_sys] first tile row of each batch system's coarse system
     const int32_t *csys_ce0;     // [n_sys+1] first coarse element of each batch system
+    const int32_t *coarse_sys;   // [n_coarse] batch system of each coarse element
     const double *part;          // Schwarz row partials
     const double *colpart;       // Schwarz column partials
     const double *itemdot;
@@ -158,8 +167,9 @@ enum LocalStorage { STORE_F64 = 0, STORE_F32 = 1, STORE_BF16 = 2 };
 
 hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t s);
+// One workgroup per item; with events, the dispatch records its own start and stop times in them.
 hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store,
-                          int max_nj, hipStream_t s);
+                          int max_nj, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // LDS bytes the Schwarz kernel needs for items of up to max_nj tiles.
 size_t schwarz_lds_bytes(int local_store, int coarse_store, int max_nj);
 hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s);
@@ -168,6 +178,11 @@ hipError_t launch_project_p0(const double *vals, int ncomp, int64_t n_elem, int 
                              double *coeff, hipStream_t s);
 hipError_t launch_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit, int reset_ionic,
                                hipStream_t s);
+// One block per system: sc[s].pq_sum = sum of the system's SpMV partials
+// (slot 0, stride 2) if which == 0, sc[s].rz_sum = sum of its Schwarz shares
+// if which == 1.
+hipError_t launch_reduce(const double *part, const int32_t *ranges, int n_sys, int which, DevScalars *sc,
+                         hipStream_t s);
 // Sums the SpMV partials (stride 2, slot `slot`) of each system into sc[s].tr.
 hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_sys, int slot, DevScalars *sc,
                                hipStream_t s);
@@ -176,6 +191,7 @@ hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_
 struct ChooseArgs {
     int nd;
     const int32_t *grp_ptr, *grp_elems, *grp_sys;  // update chunks
+    const int32_t *sys_chunk0;                     // [n_sys] first chunk of each system
     int n_grp;
     const double *part;      // SpMV partials of the guess residual
     const double *g, *r_g;   // guess and its residual

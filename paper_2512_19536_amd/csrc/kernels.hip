@@ -19,6 +19,7 @@
 // adds the partials of its system in a fixed order in each of its workgroups.
 // All sums therefore have a fixed order and two runs give bitwise-equal
 // results; a system gives the same bits alone or inside a batch.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -59,10 +60,19 @@ __device__ inline void block_sum(double (&v)[NV], double (&tot)[NV]) {
 }
 
 // Sum of part[k * stride + slot], k < n, in a fixed order, in every thread.
+// Four independent running sums per thread keep four loads in flight.
 template <int BS>
 __device__ inline double block_sum_partials(const double *part, int n, int stride, int slot) {
-    double v[1] = {0.0}, t[1];
-    for (int k = threadIdx.x; k < n; k += BS) v[0] += part[(int64_t)k * stride + slot];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = threadIdx.x;
+    for (; k + 3 * BS < n; k += 4 * BS) {
+        a0 += part[(int64_t)k * stride + slot];
+        a1 += part[(int64_t)(k + BS) * stride + slot];
+        a2 += part[(int64_t)(k + 2 * BS) * stride + slot];
+        a3 += part[(int64_t)(k + 3 * BS) * stride + slot];
+    }
+    for (; k < n; k += BS) a0 += part[(int64_t)k * stride + slot];
+    double v[1] = {(a0 + a1) + (a2 + a3)}, t[1];
     block_sum<1, BS>(v, t);
     return t[0];
 }
@@ -88,44 +98,71 @@ __device__ inline int block_bcast(int v) {
 // owns output row i of the group's r-th element.  Group values are stored
 // slot-major so that for every (slot s, trial index j) a wavefront reads G*ND
 // consecutive doubles:  val[((s * ND + j) * G + r) * ND + i] = K_{row_r, col_{s,r}}[i][j].
-// One workgroup per group: its WPG wavefronts take the slots round-robin and
-// their partial sums are added in wave order through LDS.
+// A workgroup owns a contiguous run of groups (of one system) and writes one
+// partial sum; its WPG wavefronts take each group's slots round-robin and
+// their sums are added in wave order through LDS (double-buffered, one
+// barrier per group).
 template <int ND, int WPG>
 __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
-    if (a.mode == SPMV_PQ && a.sc[A.grp_sys[blockIdx.x]].done) return;
-    __shared__ double s_acc[WPG][64];
+    const int64_t g_begin = A.wg_g0[blockIdx.x], g_end = A.wg_g0[blockIdx.x + 1];
+    if (a.mode == SPMV_PQ && a.sc[A.grp_sys[g_begin]].done) return;
+    __shared__ double s_acc[2][WPG][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t g = blockIdx.x;
     const int r = lane / ND, i = lane - (lane / ND) * ND;
-    double acc = 0.0;
-    if (r < G) {
-        const int64_t s0 = A.grp_slot_off[g], ns = A.grp_slot_off[g + 1] - s0;
-        const int32_t *colp = A.grp_col + s0 * G + r;
-        const double *vp = A.grp_val + s0 * G * ND * ND + lane;
-        for (int64_t s = w; s < ns; s += WPG) {
-            const double *xb = a.x + (int64_t)colp[s * G] * ND;
-            const double *vs = vp + s * G * ND * ND;
-            double v[ND];
-#pragma unroll
-            for (int j = 0; j < ND; ++j) v[j] = vs[j * G * ND];
-#pragma unroll
-            for (int j = 0; j < ND; ++j) acc = fma(v[j], xb[j], acc);
-        }
-    }
-    if (WPG > 1) {
-        s_acc[w][lane] = acc;
-        __syncthreads();
-        if (w == 0) {
-            acc = s_acc[0][lane];
-#pragma unroll
-            for (int k = 1; k < WPG; ++k) acc += s_acc[k][lane];
-        }
-    }
-    if (w != 0) return;  // wave 0 finishes the group
+    // U slots per loop trip, all of their loads issued before the first
+    // multiply, so a wavefront keeps U slots of the matrix in flight
+    constexpr int U = ND <= 6 ? 4 : (ND <= 10 ? 2 : 1);
     double part[2] = {0.0, 0.0};
-    const int row = (r < G) ? A.grp_rows[g * G + r] : -1;
-    if (row >= 0) {
+    int par = 0;
+    for (int64_t g = g_begin; g < g_end; ++g) {
+        double acc = 0.0;
+        if (r < G) {
+            const int64_t s0 = A.grp_slot_off[g], ns = A.grp_slot_off[g + 1] - s0;
+            const int32_t *colp = A.grp_col + s0 * G + r;
+            const double *vp = A.grp_val + s0 * G * ND * ND + lane;
+            double accu[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) accu[u] = 0.0;
+            for (int64_t s = w; s < ns; s += U * WPG) {
+                int c[U];
+                double v[U][ND];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t su = s + u * WPG;
+                    c[u] = su < ns ? colp[su * G] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double *vs = vp + (s + u * WPG) * G * ND * ND;
+#pragma unroll
+                    for (int j = 0; j < ND; ++j) v[u][j] = c[u] >= 0 ? vs[j * G * ND] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (c[u] < 0) continue;
+                    const double *xb = a.x + (int64_t)c[u] * ND;
+#pragma unroll
+                    for (int j = 0; j < ND; ++j) accu[u] = fma(v[u][j], xb[j], accu[u]);
+                }
+            }
+            acc = accu[0];
+#pragma unroll
+            for (int u = 1; u < U; ++u) acc += accu[u];
+        }
+        if (WPG > 1) {
+            s_acc[par][w][lane] = acc;
+            __syncthreads();
+            if (w == 0) {
+                acc = s_acc[par][0][lane];
+#pragma unroll
+                for (int k = 1; k < WPG; ++k) acc += s_acc[par][k][lane];
+            }
+            par ^= 1;
+        }
+        if (w != 0) continue;  // wave 0 finishes the group
+        const int row = (r < G) ? A.grp_rows[g * G + r] : -1;
+        if (row < 0) continue;
         const int64_t idx = (int64_t)row * ND + i;
         switch (a.mode) {
         case SPMV_PLAIN:
@@ -133,15 +170,15 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
             break;
         case SPMV_PQ:
             a.y[idx] = acc;
-            part[0] = a.x[idx] * acc;
+            part[0] = fma(a.x[idx], acc, part[0]);
             break;
         case SPMV_RESID: {
             const double bv = a.b[idx], rv = bv - acc;
             a.y[idx] = rv;
             if (a.xcopy) a.xcopy[idx] = a.x[idx];
             if (a.u_prev) a.u_prev[idx] = a.x[idx];
-            part[0] = bv * bv;
-            part[1] = rv * rv;
+            part[0] = fma(bv, bv, part[0]);
+            part[1] = fma(rv, rv, part[1]);
             break;
         }
         case SPMV_STEP:
@@ -159,38 +196,42 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
                 a.y[idx] = bv - acc;  // r0 = b - K u  (x0 = u)
                 a.u_prev[idx] = ur[i];
                 if (a.xcopy) a.xcopy[idx] = ur[i];
-                part[0] = bv * bv;
+                part[0] = fma(bv, bv, part[0]);
             }
             break;
         }
         }
     }
-    if (a.mode == SPMV_PLAIN || a.mode == SPMV_RHS) return;
+    if (w != 0 || a.mode == SPMV_PLAIN || a.mode == SPMV_RHS) return;
     wave_sum<2>(part);
     if (lane == 0) {
-        a.part[2 * g] = part[0];
-        a.part[2 * g + 1] = part[1];
+        a.part[2 * blockIdx.x] = part[0];
+        a.part[2 * blockIdx.x + 1] = part[1];
     }
 }
 
 // ---------------------------------------------------------------------------
-// alpha = (r, z) / (p, q); x += alpha p, r -= alpha q; per-chunk ||r||^2 and
-// coarse restriction shares of P^T r.  One workgroup per update chunk (a run
-// of elements inside one coarse element); the Schwarz kernel adds the shares
-// of a coarse element in chunk order when it gathers r0.
+// alpha = (r, z) / (p, q); x += alpha p, r -= alpha q; ||r||^2 and the coarse
+// restriction shares of P^T r.  A workgroup owns a contiguous run of update
+// chunks (runs of elements inside one coarse element, all of one system):
+// it writes one ||r||^2 partial and, per chunk, the chunk's restriction
+// share, which the Schwarz kernel adds in chunk order when it gathers r0.
 template <int ND, int NQ>
 __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
-    const int c = blockIdx.x, b = a.grp_sys[c];
+    const int wg = blockIdx.x;
+    const int c_begin = a.wg_c0[wg], c_end = a.wg_c0[wg + 1];
+    const int b = a.grp_sys[c_begin];
     DevScalars *sc = a.sc + b;
-    // the owner chunk may set `done` during this launch
+    // the owner workgroup may set `done` during this launch
     if (block_bcast<128>(threadIdx.x == 0 ? sc->done : 0)) return;
     double alpha = 0.0;
     if (!a.init) {
         const int g0 = a.rng.spmv[b];
-        const double pq = block_sum_partials<128>(a.pqpart + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 0);
+        const double pq = a.pre_pq ? sc->pq_sum
+                                   : block_sum_partials<128>(a.pqpart + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 0);
         const int j = sc->iters + 1;
         alpha = sc->rz[(j - 1) & 1] / pq;
-        if (c == a.rng.upd[b] && threadIdx.x == 0) {
+        if (wg == a.rng.upd[b] && threadIdx.x == 0) {
             sc->pq = pq;
             sc->alpha = alpha;
             sc->jcur = j;
@@ -203,35 +244,40 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
             }
         }
     }
-    const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * ND;
-    constexpr int NV = 1 + (NQ > 0 ? NQ : 1);
-    double v[NV];
+    double rr = 0.0;
+    for (int c = c_begin; c < c_end; ++c) {
+        const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * ND;
+        constexpr int NV = NQ > 0 ? NQ : 1;
+        double v[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int d = threadIdx.x; d < ndof; d += 128) {
-        const int le = d / ND, i = d - le * ND;
-        const int64_t idx = (int64_t)a.grp_elems[e0 + le] * ND + i;
-        double rv = a.r[idx];
-        if (!a.init) {
-            a.x[idx] = fma(alpha, a.p[idx], a.x[idx]);
-            rv = fma(-alpha, a.q[idx], rv);
-            a.r[idx] = rv;
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
+        for (int d = threadIdx.x; d < ndof; d += 128) {
+            const int le = d / ND, i = d - le * ND;
+            const int64_t idx = (int64_t)a.grp_elems[e0 + le] * ND + i;
+            double rv = a.r[idx];
+            if (!a.init) {
+                a.x[idx] = fma(alpha, a.p[idx], a.x[idx]);
+                rv = fma(-alpha, a.q[idx], rv);
+                a.r[idx] = rv;
+            }
+            rr = fma(rv, rv, rr);
+            if (NQ > 0) {
+                const double *Pr = a.P + idx * NQ;
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) v[j] = fma(Pr[j], rv, v[j]);
+            }
         }
-        v[0] = fma(rv, rv, v[0]);
         if (NQ > 0) {
-            const double *Pr = a.P + idx * NQ;
+            double tot[NV];
+            block_sum<NV, 128>(v, tot);
+            if (threadIdx.x == 0)
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) v[1 + j] = fma(Pr[j], rv, v[1 + j]);
+                for (int j = 0; j < NQ; ++j) a.r0part[c * NQ + j] = tot[j];
         }
     }
-    double tot[NV];
-    block_sum<NV, 128>(v, tot);
-    if (threadIdx.x == 0) {
-        a.rrpart[c] = tot[0];
-        if (NQ > 0)
-#pragma unroll
-            for (int j = 0; j < NQ; ++j) a.r0part[c * NQ + j] = tot[1 + j];
-    }
+    double v1[1] = {rr}, t1[1];
+    block_sum<1, 128>(v1, t1);
+    if (threadIdx.x == 0) a.rrpart[wg] = t1[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -463,6 +509,8 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     __syncthreads();
 }
 
+// One workgroup per item: the most tile loads in flight.  Each workgroup
+// writes its item's row partial and its share of (r, z).
 template <typename EL, typename EC>
 __global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a, int max_nj) {
     if (a.mode != 0 && a.sc[a.item_owner[blockIdx.x]].done) return;
@@ -534,7 +582,8 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
             // the owner block may set `done` during this launch
             if (block_bcast<256>(threadIdx.x == 0 ? sc->done : 0)) continue;
             const int it0 = a.rng.item[b];
-            const double rz = block_sum_partials<256>(a.itemdot + it0, a.rng.item[b + 1] - it0, 1, 0);
+            const double rz = a.pre_rz ? sc->rz_sum
+                                       : block_sum_partials<256>(a.itemdot + it0, a.rng.item[b + 1] - it0, 1, 0);
             const int j = a.mode == 2 ? sc->jcur : 0;
             const double bt = a.mode == 2 ? rz / sc->rz[(j - 1) & 1] : 0.0;
             if (my == b) {
@@ -576,22 +625,73 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
             }
         }
     }
+    // coarse values z0 of the block's coarse elements, once per block: the
+    // block's elements usually lie in one or two coarse elements (numbered
+    // contiguously), so the block computes their KMAX * NQ values into LDS
+    constexpr int KMAX = 8;
+    __shared__ double s_z0[KMAX * (NQ > 0 ? NQ : 1)];
+    __shared__ int s_cr[2];
+    int c_lo = 0, n_c = KMAX + 1;
+    if (NQ > 0) {
+        if (threadIdx.x == 0) {
+            s_cr[0] = a.elem_coarse[i0 / nd];
+            s_cr[1] = a.elem_coarse[i1 / nd];
+        }
+        __syncthreads();
+        c_lo = s_cr[0];
+        n_c = s_cr[1] - c_lo + 1;
+        // the range holds every element's coarse element only if it is monotone over the block
+        const int ce = idx < n ? a.elem_coarse[idx / nd] : c_lo;
+        const int bad = __syncthreads_or(ce < c_lo || ce >= c_lo + n_c);
+        if (bad || n_c > KMAX || n_c < 1) n_c = KMAX + 1;
+        if (n_c <= KMAX) {
+            if ((int)threadIdx.x < n_c * NQ) {
+                const int c = c_lo + (int)threadIdx.x / NQ, j = (int)threadIdx.x % NQ;
+                const int b = a.coarse_sys[c];
+                const int gi = (c - a.csys_ce0[b]) * NQ + j;
+                s_z0[threadIdx.x] = tile_row_value(a, a.coarse_rt0[b] + (gi >> 6), gi & 63);
+            }
+            __syncthreads();
+        }
+    }
     if (!active) return;
     const int dr = a.dof_rt[idx];
     double zz = tile_row_value(a, dr >> 6, dr & 63);
     if (NQ > 0) {
         const int64_t e = idx / nd;
-        const int g0 = (a.elem_coarse[e] - a.csys_ce0[my]) * NQ;
-        const int rt0 = a.coarse_rt0[my];
+        const int ce = a.elem_coarse[e];
         const double *Pr = a.P + idx * NQ;
+        if (n_c <= KMAX) {
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-            const int gi = g0 + j;
-            zz = fma(Pr[j], tile_row_value(a, rt0 + (gi >> 6), gi & 63), zz);
+            for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
+        } else {
+            const int g0 = (ce - a.csys_ce0[my]) * NQ;
+            const int rt0 = a.coarse_rt0[my];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+                const int gi = g0 + j;
+                zz = fma(Pr[j], tile_row_value(a, rt0 + (gi >> 6), gi & 63), zz);
+            }
         }
     }
     if (a.mode == 2) zz = fma(beta, a.p[idx], zz);
     a.p[idx] = zz;
+}
+
+// The block size of each sum equals that of the kernel that would otherwise
+// form it (update: 128, p-update: 256), so both paths add in the same order
+// and give the same bits.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_reduce(const double *part, const int32_t *ranges, int which,
+                                               DevScalars *sc) {
+    const int b = blockIdx.x, g0 = ranges[b];
+    if (which == 0) {
+        const double t = block_sum_partials<BS>(part + 2 * (int64_t)g0, ranges[b + 1] - g0, 2, 0);
+        if (threadIdx.x == 0) sc[b].pq_sum = t;
+    } else {
+        const double t = block_sum_partials<BS>(part + g0, ranges[b + 1] - g0, 1, 0);
+        if (threadIdx.x == 0) sc[b].rz_sum = t;
+    }
 }
 
 // sc[b].tr = sum of the SpMV partials (slot `slot`) of system b; one block per system.
@@ -852,7 +952,7 @@ __global__ __launch_bounds__(128) void k_choose(ChooseArgs a) {
     const int g0 = a.rng.spmv[b];
     const double rg = block_sum_partials<128>(a.part + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 1);
     const bool use = rg < sc->tr;
-    if (c == a.rng.upd[b] && threadIdx.x == 0) sc->guess = use ? 1 : 0;
+    if (c == a.sys_chunk0[b] && threadIdx.x == 0) sc->guess = use ? 1 : 0;
     if (!use) return;
     const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * a.nd;
     for (int d = threadIdx.x; d < ndof; d += 128) {
@@ -889,7 +989,7 @@ __global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
 // launchers
 template <int ND, int WPG>
 static hipError_t spmv_nd_w(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv<ND, WPG>), dim3((unsigned)A.n_groups), dim3(64 * WPG), 0, s, A, a);
+    hipLaunchKernelGGL((k_spmv<ND, WPG>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
     return hipGetLastError();
 }
 
@@ -905,7 +1005,7 @@ static hipError_t spmv_nd(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) 
 }
 
 hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    if (A.n_groups <= 0) return hipSuccess;
+    if (A.n_wg <= 0) return hipSuccess;
     switch (A.nd) {
     case 3: return spmv_nd<3>(A, a, s);
     case 4: return spmv_nd<4>(A, a, s);
@@ -921,16 +1021,16 @@ hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
 template <int ND>
 static hipError_t update_nd(const UpdateArgs &a, hipStream_t s) {
     switch (a.nq0) {
-    case 0: hipLaunchKernelGGL((k_update<ND, 0>), dim3(a.n_grp), dim3(128), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_update<ND, 3>), dim3(a.n_grp), dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_update<ND, 4>), dim3(a.n_grp), dim3(128), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_update<ND, 0>), dim3(a.n_wg), dim3(128), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_update<ND, 3>), dim3(a.n_wg), dim3(128), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_update<ND, 4>), dim3(a.n_wg), dim3(128), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_update(const UpdateArgs &a, hipStream_t s) {
-    if (a.n_grp <= 0) return hipSuccess;
+    if (a.n_wg <= 0) return hipSuccess;
     switch (a.nd) {
     case 3: return update_nd<3>(a, s);
     case 4: return update_nd<4>(a, s);
@@ -968,9 +1068,13 @@ static size_t schwarz_bytes_t(int max_nj) {
 }
 
 template <typename EL, typename EC>
-static hipError_t schwarz_t(const SchwarzArgs &a, int n_items, int max_nj, hipStream_t s) {
+static hipError_t schwarz_t(const SchwarzArgs &a, int n_wg, int max_nj, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
     const size_t lds = schwarz_bytes_t<EL, EC>(max_nj);
-    hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_items), dim3(256), lds, s, a, max_nj);
+    if (e0 || e1)  // the dispatch itself records the start and stop times
+        hipExtLaunchKernelGGL(k_schwarz<EL, EC>, dim3(n_wg), dim3(256), (uint32_t)lds, s, e0, e1, 0u, a, max_nj);
+    else
+        hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_wg), dim3(256), lds, s, a, max_nj);
     return hipGetLastError();
 }
 
@@ -983,20 +1087,20 @@ size_t schwarz_lds_bytes(int local_store, int coarse_store, int max_nj) {
     return l > c ? l : c;
 }
 
-hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store, int max_nj,
-                          hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
+hipError_t launch_schwarz(const SchwarzArgs &a, int n_wg, int local_store, int coarse_store, int max_nj,
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (n_wg <= 0) return hipSuccess;
     if (coarse_store == STORE_F64) {
         switch (local_store) {
-        case STORE_F64: return schwarz_t<double, double>(a, n_items, max_nj, s);
-        case STORE_F32: return schwarz_t<float, double>(a, n_items, max_nj, s);
-        case STORE_BF16: return schwarz_t<uint16_t, double>(a, n_items, max_nj, s);
+        case STORE_F64: return schwarz_t<double, double>(a, n_wg, max_nj, s, e0, e1);
+        case STORE_F32: return schwarz_t<float, double>(a, n_wg, max_nj, s, e0, e1);
+        case STORE_BF16: return schwarz_t<uint16_t, double>(a, n_wg, max_nj, s, e0, e1);
         }
     } else {
         switch (local_store) {
-        case STORE_F64: return schwarz_t<double, float>(a, n_items, max_nj, s);
-        case STORE_F32: return schwarz_t<float, float>(a, n_items, max_nj, s);
-        case STORE_BF16: return schwarz_t<uint16_t, float>(a, n_items, max_nj, s);
+        case STORE_F64: return schwarz_t<double, float>(a, n_wg, max_nj, s, e0, e1);
+        case STORE_F32: return schwarz_t<float, float>(a, n_wg, max_nj, s, e0, e1);
+        case STORE_BF16: return schwarz_t<uint16_t, float>(a, n_wg, max_nj, s, e0, e1);
         }
     }
     return hipErrorInvalidValue;
@@ -1019,6 +1123,16 @@ hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_
                                hipStream_t s) {
     if (n_sys <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sum_partials, dim3(n_sys), dim3(256), 0, s, part, ranges, slot, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *part, const int32_t *ranges, int n_sys, int which, DevScalars *sc,
+                         hipStream_t s) {
+    if (n_sys <= 0) return hipSuccess;
+    if (which == 0)
+        hipLaunchKernelGGL(k_reduce<128>, dim3(n_sys), dim3(128), 0, s, part, ranges, which, sc);
+    else
+        hipLaunchKernelGGL(k_reduce<256>, dim3(n_sys), dim3(256), 0, s, part, ranges, which, sc);
     return hipGetLastError();
 }
 
