@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--item-kb", type=int, default=None, help="Schwarz work-item size (KiB of tiles)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=1024)
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="precision form: steps also taken with FP64 Schwarz solves to report the error")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; a multi-GPU run is not provided "
@@ -410,6 +412,29 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
+    # precision form: error per step against the same steps taken with FP64
+    # Schwarz solves (the FP64 path is the one checked against the oracle)
+    prec_err = None
+    if pr.local_prec != "f64" and args.compare_steps > 0:
+        log(f"[bench] precision form: {args.compare_steps} steps beside an FP64-Schwarz context")
+        ref = from_problem(pr, device=dev, local_prec="f64", coarse_prec="f64",
+                           options={_lib.PDG_OPT_TRUE_RESIDUAL: 1})
+        ctx.set_option(_lib.PDG_OPT_TRUE_RESIDUAL, 1)
+        prec_err = []
+        for k in range(args.compare_steps):
+            u2, up2, y2 = U.clone(), Up.clone(), Y.clone()
+            i_lo = ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
+            i_hi = ref.step(u2, up2, y2, None, pr.tol, pr.maxit)
+            torch.cuda.synchronize()
+            err = float((U - u2).norm() / u2.norm())
+            prec_err.append({"step": k, "rel_l2_vs_f64": err, "iters": i_lo["iters"], "iters_f64": i_hi["iters"],
+                             "true_relres": i_lo["true_relres"]})
+            log(f"[bench]   step {k}: rel L2 vs FP64 {err:.2e}, iters {i_lo['iters']} (FP64 {i_hi['iters']}), "
+                f"true relres {i_lo['true_relres']:.2e}")
+        ctx.set_option(_lib.PDG_OPT_TRUE_RESIDUAL, 0)
+        del ref
+        torch.cuda.empty_cache()
+
     tag = pr.name + ("" if pr.local_prec == "f64" else "_" + pr.local_prec)
     traffic = traffic_from_profiles(tag, k_bytes)
     roof = {
@@ -450,6 +475,7 @@ def main():
             "n_dof": pr.n_dof, "n_elem": pr.n_elem, "p": pr.p, "n_sub": pr.n_sub,
         },
         "pcg_iters": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
+        "precision_form_error": prec_err,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

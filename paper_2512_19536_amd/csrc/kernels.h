@@ -167,8 +167,9 @@ enum LocalStorage { STORE_F64 = 0, STORE_F32 = 1, STORE_BF16 = 2 };
 
 hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t s);
-// One workgroup per item; with events, the dispatch records its own start and stop times in them.
-hipError_t launch_schwarz(const SchwarzArgs &a, int n_items, int local_store, int coarse_store,
+// One block per item (grid = number of items); with events, the dispatch
+// records its own start and stop times in them.
+hipError_t launch_schwarz(const SchwarzArgs &a, int grid, int local_store, int coarse_store,
                           int max_nj, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // LDS bytes the Schwarz kernel needs for items of up to max_nj tiles.
 size_t schwarz_lds_bytes(int local_store, int coarse_store, int max_nj);

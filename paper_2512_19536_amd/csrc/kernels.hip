@@ -509,14 +509,15 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     __syncthreads();
 }
 
-// One workgroup per item: the most tile loads in flight.  Each workgroup
-// writes its item's row partial and its share of (r, z).
+// One workgroup per item: a fresh workgroup hides the start-up latency of
+// the previous one on its CU (a persistent loop over items does not).
 template <typename EL, typename EC>
 __global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a, int max_nj) {
-    if (a.mode != 0 && a.sc[a.item_owner[blockIdx.x]].done) return;
+    const int item = blockIdx.x;
+    if (a.mode != 0 && a.sc[a.item_owner[item]].done) return;
     extern __shared__ double smem[];
     __shared__ double yout[TILE];
-    const int item = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int s = a.item_sys[item], I = a.item_row[item], j0 = a.item_j0[item], nj = a.item_nj[item];
     const bool coarse = s >= a.n_sub;
     double r_own = 0.0, dcol = 0.0;
@@ -1068,13 +1069,13 @@ static size_t schwarz_bytes_t(int max_nj) {
 }
 
 template <typename EL, typename EC>
-static hipError_t schwarz_t(const SchwarzArgs &a, int n_wg, int max_nj, hipStream_t s, hipEvent_t e0,
+static hipError_t schwarz_t(const SchwarzArgs &a, int grid, int max_nj, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1) {
     const size_t lds = schwarz_bytes_t<EL, EC>(max_nj);
     if (e0 || e1)  // the dispatch itself records the start and stop times
-        hipExtLaunchKernelGGL(k_schwarz<EL, EC>, dim3(n_wg), dim3(256), (uint32_t)lds, s, e0, e1, 0u, a, max_nj);
+        hipExtLaunchKernelGGL(k_schwarz<EL, EC>, dim3(grid), dim3(256), (uint32_t)lds, s, e0, e1, 0u, a, max_nj);
     else
-        hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(n_wg), dim3(256), lds, s, a, max_nj);
+        hipLaunchKernelGGL((k_schwarz<EL, EC>), dim3(grid), dim3(256), lds, s, a, max_nj);
     return hipGetLastError();
 }
 
@@ -1087,20 +1088,20 @@ size_t schwarz_lds_bytes(int local_store, int coarse_store, int max_nj) {
     return l > c ? l : c;
 }
 
-hipError_t launch_schwarz(const SchwarzArgs &a, int n_wg, int local_store, int coarse_store, int max_nj,
+hipError_t launch_schwarz(const SchwarzArgs &a, int grid, int local_store, int coarse_store, int max_nj,
                           hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (n_wg <= 0) return hipSuccess;
+    if (grid <= 0) return hipSuccess;
     if (coarse_store == STORE_F64) {
         switch (local_store) {
-        case STORE_F64: return schwarz_t<double, double>(a, n_wg, max_nj, s, e0, e1);
-        case STORE_F32: return schwarz_t<float, double>(a, n_wg, max_nj, s, e0, e1);
-        case STORE_BF16: return schwarz_t<uint16_t, double>(a, n_wg, max_nj, s, e0, e1);
+        case STORE_F64: return schwarz_t<double, double>(a, grid, max_nj, s, e0, e1);
+        case STORE_F32: return schwarz_t<float, double>(a, grid, max_nj, s, e0, e1);
+        case STORE_BF16: return schwarz_t<uint16_t, double>(a, grid, max_nj, s, e0, e1);
         }
     } else {
         switch (local_store) {
-        case STORE_F64: return schwarz_t<double, float>(a, n_wg, max_nj, s, e0, e1);
-        case STORE_F32: return schwarz_t<float, float>(a, n_wg, max_nj, s, e0, e1);
-        case STORE_BF16: return schwarz_t<uint16_t, float>(a, n_wg, max_nj, s, e0, e1);
+        case STORE_F64: return schwarz_t<double, float>(a, grid, max_nj, s, e0, e1);
+        case STORE_F32: return schwarz_t<float, float>(a, grid, max_nj, s, e0, e1);
+        case STORE_BF16: return schwarz_t<uint16_t, float>(a, grid, max_nj, s, e0, e1);
         }
     }
     return hipErrorInvalidValue;
