@@ -1230,6 +1230,8 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         c->dA.nd = nd;
         c->dA.G = c->G;
         c->dA.wpg = c->spmv_wpg;
+        // matrices that cannot stay in the 256 MB last-level cache stream non-temporally
+        c->dA.nt = c->grp_val.size() * 8 > ((size_t)192 << 20) ? 1 : 0;
         c->dA.n_rows = m.n_elem;
         c->dA.n_groups = c->n_groups;
         c->dA.grp_rows = wptr<int32_t>(c, w.grows);

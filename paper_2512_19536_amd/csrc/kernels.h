@@ -49,6 +49,7 @@ struct SysRanges {
 struct DevMatrix {
     int nd, G;              // block size, block rows per group
     int wpg;                // wavefronts per group (1, 2, 4 or 8)
+    int nt;                 // 1: stream the values with non-temporal loads (matrix larger than the cache)
     int64_t n_rows, n_groups;
     const int32_t *grp_rows;     // [n_groups*G] row ids (-1 = padding)
     const int64_t *grp_slot_off; // [n_groups+1] slot offsets

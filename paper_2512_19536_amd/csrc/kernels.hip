@@ -102,7 +102,9 @@ __device__ inline int block_bcast(int v) {
 // partial sum; its WPG wavefronts take each group's slots round-robin and
 // their sums are added in wave order through LDS (double-buffered, one
 // barrier per group).
-template <int ND, int WPG>
+// Matrices larger than the last-level cache stream their values with
+// non-temporal loads (NT), smaller ones stay cacheable across iterations.
+template <int ND, int WPG, bool NT>
 __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
     const int64_t g_begin = A.wg_g0[blockIdx.x], g_end = A.wg_g0[blockIdx.x + 1];
@@ -136,7 +138,8 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
                 for (int u = 0; u < U; ++u) {
                     const double *vs = vp + (s + u * WPG) * G * ND * ND;
 #pragma unroll
-                    for (int j = 0; j < ND; ++j) v[u][j] = c[u] >= 0 ? vs[j * G * ND] : 0.0;
+                    for (int j = 0; j < ND; ++j)
+                        v[u][j] = c[u] >= 0 ? (NT ? __builtin_nontemporal_load(vs + j * G * ND) : vs[j * G * ND]) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -290,6 +293,8 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
 // of a wavefront reads whole contiguous tile rows; the next tile is loaded
 // while the current one is multiplied.  Items hold ~256 KB of tiles, so the
 // grid is many similar-sized workgroups.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename E> struct AccT { using T = float; };
 template <> struct AccT<double> { using T = double; };
 
@@ -398,10 +403,13 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     auto tile_ptr = [&](int J) -> const E * {
         return tiles + (toff + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE) + (rg * RPT) * TILE + cg * CW;
     };
+    // Tiles are read once per apply and exceed the last-level cache: non-temporal
+    // loads keep them from evicting data that is reused (the SpMV matrix).
     auto load = [&](V (&buf)[RPT], int J) {
         const E *tp = tile_ptr(J);
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) buf[k] = *reinterpret_cast<const V *>(tp + k * TILE);
+        for (int k = 0; k < RPT; ++k)
+            buf[k] = __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + k * TILE)));
     };
     A accR[RPT];
 #pragma unroll
@@ -990,7 +998,10 @@ __global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
 // launchers
 template <int ND, int WPG>
 static hipError_t spmv_nd_w(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv<ND, WPG>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+    if (A.nt)
+        hipLaunchKernelGGL((k_spmv<ND, WPG, true>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+    else
+        hipLaunchKernelGGL((k_spmv<ND, WPG, false>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
     return hipGetLastError();
 }
 

@@ -251,7 +251,9 @@ def evaluate(mlp, problem, n_steps, device="cuda:0", options=None, extrapolate_o
     and from the learned guess -- and iterations and times are recorded; the
     trajectory continues with the plain result."""
     torch = mlp.torch
-    ctx = from_problem(problem, device=device, options=options)
+    opts = dict(options or {})
+    opts[_lib.PDG_OPT_KERNEL_TIMING] = 1
+    ctx = from_problem(problem, device=device, options=opts)
     U, Up, Y = initial_state(ctx, problem)
     n_elem, nd = problem.n_elem, problem.nd
     hist = [U.clone()]
@@ -312,5 +314,6 @@ def evaluate(mlp, problem, n_steps, device="cuda:0", options=None, extrapolate_o
         if log and (k % 20 == 0 or k == n_steps - 1):
             log(f"[learned] {problem.name} step {k}: iters plain {rec['plain'][-1]} extrap {rec['extrap'][-1]} "
                 f"learned {rec['learned'][-1]} (guess used {rec['used'][-1]})")
+    rec["schwarz_timing"] = ctx.kernel_timing()  # (launches, total ms, bytes per launch)
     ctx.close()
     return rec
