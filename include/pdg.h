@@ -287,6 +287,24 @@ pdg_status pdg_guess_extrapolate(pdg_ctx *ctx, const double *u, const double *u1
 pdg_status pdg_get_system_info(const pdg_ctx *ctx, int32_t sys, pdg_solve_info *info,
                                int32_t *status);
 
+/* Condition-number estimate of the preconditioned operator from the last
+ * solve or step of system `sys` (Section 5: the extreme eigenvalues of the
+ * tridiagonal Lanczos matrix built from the PCG coefficients,
+ * T_11 = 1/alpha_1, T_jj = 1/alpha_j + beta_(j-1)/alpha_(j-1),
+ * T_j,j+1 = sqrt(beta_j)/alpha_j, j = 1..iters).  The coefficients are kept
+ * on the device during every solve (up to 2048 iterations); the eigenvalues
+ * are found on the device by Sturm-count bisection.  kappa = lambda_max /
+ * lambda_min; any output may be NULL.  Call right after the solve (PDG_ESTATE
+ * otherwise); synchronises the stream. */
+pdg_status pdg_lanczos(pdg_ctx *ctx, int32_t sys, double *kappa, double *lambda_min, double *lambda_max);
+
+/* Host copies of those PCG coefficients: alpha[j-1] = alpha_j (j = 1..m) and
+ * beta[j-1] = beta_j = (r_j, z_j) / (r_(j-1), z_(j-1)), with
+ * m = min(n, iterations of the last solve, 2048); beta_m of the converged
+ * iteration is not used by the Lanczos matrix.  Either pointer may be NULL.
+ * Call right after the solve (PDG_ESTATE otherwise); synchronises. */
+pdg_status pdg_get_pcg_coefficients(pdg_ctx *ctx, int32_t sys, double *alpha, double *beta, int32_t n);
+
 /* pdg_step for n_ctx distinct contexts at once (e.g. one context per
  * polynomial degree of a batch, each on its own stream): every context's
  * chunk of PCG iterations is queued before the host waits on any of them, so

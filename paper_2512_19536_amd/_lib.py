@@ -28,7 +28,8 @@ EXPORTS = (
     "pdg_assemble", "pdg_get_matrix", "pdg_set_ionic", "pdg_setup_preconditioner", "pdg_get_precond_sizes",
     "pdg_get_local_inverse", "pdg_get_coarse", "pdg_workspace_query", "pdg_bind_workspace", "pdg_set_option",
     "pdg_kernel_timing", "pdg_project_p0", "pdg_spmv", "pdg_precond_apply", "pdg_ionic", "pdg_rhs",
-    "pdg_solve", "pdg_step", "pdg_get_system_info", "pdg_step_batch", "pdg_autotune", "pdg_step_guess",
+    "pdg_solve", "pdg_step", "pdg_get_system_info", "pdg_step_batch", "pdg_autotune", "pdg_step_guess", "pdg_lanczos",
+    "pdg_get_pcg_coefficients",
     "pdg_guess_extrapolate", "pdg_mlp_create", "pdg_mlp_destroy", "pdg_mlp_last_error", "pdg_mlp_get_sizes",
     "pdg_mlp_bind_workspace", "pdg_mlp_set_params", "pdg_mlp_get_params", "pdg_mlp_set_normalisation",
     "pdg_mlp_set_batch", "pdg_mlp_features", "pdg_mlp_targets", "pdg_mlp_forward", "pdg_mlp_guess",
@@ -116,6 +117,8 @@ def load():
         "pdg_get_system_info": (I32, [V, I32, POINTER(PdgSolveInfo), POINTER(I32)]),
         "pdg_step_batch": (I32, [P, I32, P, P, P, P, D, I32, P]),
         "pdg_autotune": (I32, [V, I32, POINTER(PdgTuneResult)]),
+        "pdg_lanczos": (I32, [V, I32, POINTER(D), POINTER(D), POINTER(D)]),
+        "pdg_get_pcg_coefficients": (I32, [V, I32, P, P, I32]),
         "pdg_step_guess": (I32, [V, P, P, P, P, P, D, I32, POINTER(PdgSolveInfo)]),
         "pdg_guess_extrapolate": (I32, [V, P, P, P, I32, P]),
         "pdg_mlp_create": (I32, [POINTER(c_void_p), I32, V, POINTER(PdgMlpDesc)]),

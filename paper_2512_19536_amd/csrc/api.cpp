@@ -57,7 +57,7 @@ struct Ws {
     int itsys, itrow, itj0, itnj, itown, rtit0, dofrt, itdot, rowpart;
     int sysn, sysnt, systoff, sysdof0, syscb, rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
     int grpptr, grpel, upsys, cchunk, csys0, crt0, csys, rspmv, rupd, ritem, rowner;
-    int spwg, upwg, chunk0;
+    int spwg, upwg, chunk0, lanc;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
 };
 
@@ -108,6 +108,7 @@ struct pdg_ctx {
     int max_nj = 1;
     int64_t items_reserved = 0;
     int pre_pq = 0, pre_rz = 0;  // dot products pre-summed by the reduction kernel
+    bool lanczos_ok = false;     // device scalars still hold the last solve
     // group-ELL matrix (host staging)
     int G = 1;
     int64_t n_groups = 0, n_slots = 0;
@@ -177,6 +178,7 @@ constexpr int kOnePerWorkgroup = 1 << 30;
 // Above this many (consumer workgroup x partial) reads per system, a
 // dedicated reduction kernel sums the partials once instead.
 constexpr int64_t kRedundantReads = 1 << 22;
+constexpr int kLanczosCap = 2048;  // PCG coefficients kept per system for the Lanczos estimate
 
 // Splits each system's unit range [r_unit[s], r_unit[s+1]) into workgroups
 // of per_s = ceil(n_s / target) consecutive units; wg0 receives the first unit
@@ -458,6 +460,7 @@ void plan_layout(pdg_ctx *c) {
     w.sca = L.add(n_sys * sizeof(DevScalars));
     w.part = L.add(std::max<int64_t>(1, (int64_t)c->spmv_wg_g0.size()) * 2 * 8);  // SpMV partials
     w.rrpart = L.add(std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8);     // update partials
+    w.lanc = L.add((size_t)n_sys * kLanczosCap * 16);                             // PCG coefficients
 }
 
 template <class T>
@@ -589,6 +592,8 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
     u.r0part = wptr<double>(c, c->w.r0p);
     u.pqpart = wptr<double>(c, c->w.part);
     u.rrpart = wptr<double>(c, c->w.rrpart);
+    u.lanczos = sc == c->sc ? wptr<double2>(c, c->w.lanc) : nullptr;
+    u.lcap = kLanczosCap;
     u.rng = ranges(c);
     u.sc = sc;
     return u;
@@ -619,6 +624,8 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
     p.bbpart = wptr<double>(c, c->w.part);
     p.rng = ranges(c);
     p.p = out;
+    p.lanczos = sc == c->sc ? wptr<double2>(c, c->w.lanc) : nullptr;
+    p.lcap = kLanczosCap;
     p.sc = sc;
     return p;
 }
@@ -790,6 +797,7 @@ bool pcg_poll(pdg_ctx *c) {
 pdg_status pcg_end(pdg_ctx *c, pdg_solve_info *info, int *bad_sys) {
     PcgRun &R = c->run;
     R.active = false;
+    c->lanczos_ok = true;
     hipStream_t s = c->stream;
     const int n_sys = c->n_sys;
     c->last.assign(c->sc_host, c->sc_host + n_sys);
@@ -850,6 +858,7 @@ pdg_status run_pcg(pdg_ctx *c, double *x, const double *b, bool step_mode, doubl
 }
 
 void launch_ionic_step(pdg_ctx *c, const double *u, const double *u_prev, double *ions, double *I) {
+    c->lanczos_ok = false;
     HIPCHK(launch_status_reset(c->sc, c->n_sys, 0.0, 0, 1, c->stream));
     IonicArgs a{};
     a.dim = c->mesh.dim;
@@ -1472,6 +1481,40 @@ pdg_status pdg_get_system_info(const pdg_ctx *cc, int32_t sys, pdg_solve_info *i
             info->true_relres = c->last_true[sys];
         }
         if (status) *status = map_status(h.status == ST_RUN ? ST_NOCONV : h.status);
+    });
+}
+
+pdg_status pdg_lanczos(pdg_ctx *c, int32_t sys, double *kappa, double *lambda_min, double *lambda_max) {
+    return guard(c, [&] {
+        require_gpu(c);
+        if (sys < 0 || sys >= c->n_sys) throw Error(PDG_EINVAL, "system index out of range");
+        if (!c->lanczos_ok) throw Error(PDG_ESTATE, "pdg_lanczos: call right after pdg_solve / pdg_step");
+        if (c->last[sys].iters > kLanczosCap) throw Error(PDG_EINVAL, "more iterations than coefficients kept (2048)");
+        HIPCHK(launch_lanczos(wptr<double2>(c, c->w.lanc), kLanczosCap, c->n_sys, c->sc, c->stream));
+        HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, c->n_sys * sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        const DevScalars &h = c->sc_host[sys];
+        if (lambda_min) *lambda_min = h.lmin;
+        if (lambda_max) *lambda_max = h.lmax;
+        if (kappa) *kappa = h.lmax / h.lmin;
+    });
+}
+
+pdg_status pdg_get_pcg_coefficients(pdg_ctx *c, int32_t sys, double *alpha, double *beta, int32_t n) {
+    return guard(c, [&] {
+        require_gpu(c);
+        if (sys < 0 || sys >= c->n_sys || n < 0) throw Error(PDG_EINVAL, "bad arguments");
+        if (!c->lanczos_ok) throw Error(PDG_ESTATE, "pdg_get_pcg_coefficients: call right after pdg_solve / pdg_step");
+        const int m = std::min({n, c->last[sys].iters, kLanczosCap});
+        std::vector<double> h(2 * (size_t)std::max(m, 1));
+        if (m > 0)
+            HIPCHK(hipMemcpyAsync(h.data(), wptr<double2>(c, c->w.lanc) + (size_t)sys * kLanczosCap, m * 16,
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int j = 0; j < m; ++j) {
+            if (alpha) alpha[j] = h[2 * j];
+            if (beta) beta[j] = h[2 * j + 1];
+        }
     });
 }
 

@@ -22,6 +22,7 @@ struct DevScalars {
     double tr;          // ||b - K x||^2 (true residual, optional)
     double pq_sum;      // (p, q) summed by the reduction kernel (when the update kernel does not sum it)
     double rz_sum;      // (r, z) summed by the reduction kernel (when the p-update kernel does not sum it)
+    double lmin, lmax;  // extreme eigenvalues of the Lanczos matrix of the last solve (on request)
     double rz[2];       // (r, z) of the search directions of even / odd index
     int32_t done;       // 1 = this system stops
     int32_t status;     // 0 running, 1 converged, 2 zero rhs, -5 noconv, -6 breakdown, -7 nonfinite
@@ -91,6 +92,8 @@ struct UpdateArgs {
     double *r0part;         // [n_grp][nq0] per-chunk restriction, or null
     const double *pqpart;   // SpMV partials ((p, q) in slot 0)
     double *rrpart;         // [n_wg] per-workgroup ||r||^2
+    double2 *lanczos;       // [n_sys][lcap] (alpha_j, beta_j) of each iteration j, or null
+    int lcap;
     SysRanges rng;
     DevScalars *sc;
 };
@@ -148,6 +151,8 @@ struct PupdateArgs {
     const double *bbpart;        // SpMV partials of the right-hand side (init only)
     SysRanges rng;
     double *p;                   // output
+    double2 *lanczos;            // [n_sys][lcap] (alpha_j, beta_j), or null
+    int lcap;
     DevScalars *sc;
 };
 
@@ -185,6 +190,11 @@ hipError_t launch_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
 // if which == 1.
 hipError_t launch_reduce(const double *part, const int32_t *ranges, int n_sys, int which, DevScalars *sc,
                          hipStream_t s);
+// One block per system: extreme eigenvalues of the Lanczos matrix built from
+// the recorded PCG coefficients of the last solve (T_11 = 1/alpha_1,
+// T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_j,j+1 = sqrt(beta_j)/alpha_j,
+// j <= iters) into sc[s].lmin / lmax.
+hipError_t launch_lanczos(const double2 *hist, int lcap, int n_sys, DevScalars *sc, hipStream_t s);
 // Sums the SpMV partials (stride 2, slot `slot`) of each system into sc[s].tr.
 hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_sys, int slot, DevScalars *sc,
                                hipStream_t s);

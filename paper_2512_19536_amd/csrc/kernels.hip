@@ -238,6 +238,7 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
             sc->pq = pq;
             sc->alpha = alpha;
             sc->jcur = j;
+            if (a.lanczos && j <= a.lcap) a.lanczos[(int64_t)b * a.lcap + j - 1].x = alpha;
             if (!finite(pq)) {
                 sc->status = ST_NONFINITE;
                 sc->done = 1;
@@ -615,6 +616,7 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
                 sc->rz[j & 1] = rz;
                 sc->beta = bt;
                 sc->iters = j;
+                if (a.lanczos && a.mode == 2 && j <= a.lcap) a.lanczos[(int64_t)b * a.lcap + j - 1].y = bt;
                 if (a.mode == 1 && bb == 0.0) {
                     sc->status = ST_ZERO_RHS;
                     sc->done = 1;
@@ -700,6 +702,81 @@ __global__ __launch_bounds__(BS) void k_reduce(const double *part, const int32_t
     } else {
         const double t = block_sum_partials<BS>(part + g0, ranges[b + 1] - g0, 1, 0);
         if (threadIdx.x == 0) sc[b].rz_sum = t;
+    }
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal d and off-diagonal e (Sturm sequence of the LDL^T pivots).
+__device__ inline int sturm_count(const double *d, const double *e2, int m, double x, double tiny) {
+    int c = 0;
+    double q = d[0] - x;
+    for (int j = 0;;) {
+        if (q < 0.0) ++c;
+        if (++j >= m) break;
+        if (fabs(q) < tiny) q = q < 0.0 ? -tiny : tiny;
+        q = d[j] - x - e2[j - 1] / q;
+    }
+    return c;
+}
+
+// Extreme eigenvalues by parallel bisection: each round the 256 threads count
+// at 256 interior points of the bracket, which shrinks 257-fold.
+__global__ __launch_bounds__(256) void k_lanczos(const double2 *hist, int lcap, DevScalars *sc) {
+    constexpr int NT = 256, MAXM = 2048;
+    __shared__ double d[MAXM], e2[MAXM];
+    __shared__ int s_cnt[NT];
+    __shared__ double s_lo, s_hi;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int m = min(min(sc[b].iters, lcap), MAXM);
+    if (m < 1) {
+        if (t == 0) sc[b].lmin = sc[b].lmax = 1.0;
+        return;
+    }
+    const double2 *h = hist + (int64_t)b * lcap;
+    for (int j = t; j < m; j += NT) {
+        d[j] = 1.0 / h[j].x + (j > 0 ? h[j - 1].y / h[j - 1].x : 0.0);
+        if (j + 1 < m) {
+            const double off = sqrt(h[j].y) / h[j].x;
+            e2[j] = off * off;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {  // Gershgorin bracket
+        double lo = 1e300, hi = -1e300;
+        for (int j = 0; j < m; ++j) {
+            const double r = (j > 0 ? sqrt(e2[j - 1]) : 0.0) + (j + 1 < m ? sqrt(e2[j]) : 0.0);
+            lo = fmin(lo, d[j] - r);
+            hi = fmax(hi, d[j] + r);
+        }
+        s_lo = lo;
+        s_hi = hi;
+    }
+    __syncthreads();
+    const double glo = s_lo, ghi = s_hi;
+    const double tiny = 1e-300 + 1e-30 * fmax(fabs(glo), fabs(ghi));
+    for (int which = 0; which < 2; ++which) {  // 0: smallest (count >= 1), 1: largest (count >= m)
+        const int target = which == 0 ? 1 : m;
+        double lo = glo, hi = ghi;
+        for (int round = 0; round < 8; ++round) {
+            const double x = lo + (hi - lo) * (double)(t + 1) / (double)(NT + 1);
+            s_cnt[t] = sturm_count(d, e2, m, x, tiny) >= target;
+            __syncthreads();
+            if (t == 0) {
+                int k = 0;
+                while (k < NT && !s_cnt[k]) ++k;  // first point whose count reaches the target
+                const double w = (hi - lo) / (double)(NT + 1);
+                s_hi = k < NT ? lo + w * (k + 1) : hi;
+                s_lo = lo + w * k;
+            }
+            __syncthreads();
+            lo = s_lo;
+            hi = s_hi;
+            __syncthreads();
+        }
+        if (t == 0) {
+            if (which == 0) sc[b].lmin = 0.5 * (lo + hi);
+            else sc[b].lmax = 0.5 * (lo + hi);
+        }
     }
 }
 
@@ -1145,6 +1222,12 @@ hipError_t launch_reduce(const double *part, const int32_t *ranges, int n_sys, i
         hipLaunchKernelGGL(k_reduce<128>, dim3(n_sys), dim3(128), 0, s, part, ranges, which, sc);
     else
         hipLaunchKernelGGL(k_reduce<256>, dim3(n_sys), dim3(256), 0, s, part, ranges, which, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos(const double2 *hist, int lcap, int n_sys, DevScalars *sc, hipStream_t s) {
+    if (n_sys <= 0 || !hist) return hipSuccess;
+    hipLaunchKernelGGL(k_lanczos, dim3(n_sys), dim3(256), 0, s, hist, lcap, sc);
     return hipGetLastError();
 }
 

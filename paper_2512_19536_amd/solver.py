@@ -191,6 +191,19 @@ class Context:
     def guess_extrapolate(self, u, u1, u2, order, guess):
         self._call("pdg_guess_extrapolate", _ptr(u), _ptr(u1), _ptr(u2), int(order), _ptr(guess))
 
+    def lanczos(self, sys=0):
+        """(kappa, lambda_min, lambda_max) of the last solve's Lanczos matrix."""
+        k, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._call("pdg_lanczos", int(sys), ctypes.byref(k), ctypes.byref(lo), ctypes.byref(hi))
+        return k.value, lo.value, hi.value
+
+    def pcg_coefficients(self, sys=0, n=2048):
+        """(alpha_1..alpha_m, beta_1..beta_m) recorded during the last solve."""
+        a, b = np.zeros(n), np.zeros(n)
+        self._call("pdg_get_pcg_coefficients", int(sys), _ptr(a), _ptr(b), int(n))
+        m = self.system_info(sys)["iters"]
+        return a[:min(m, n)], b[:min(m, n)]
+
     def system_info(self, sys):
         info, st = PdgSolveInfo(), ctypes.c_int32()
         self._call("pdg_get_system_info", int(sys), ctypes.byref(info), ctypes.byref(st))
