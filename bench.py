@@ -320,12 +320,146 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def _mesh_h(mesh):
+    """Largest element diameter (max vertex-vertex distance over the cells)."""
+    import numpy as np
+    h = 0.0
+    for e in range(mesh.n_elem):
+        v = mesh.cell_geom[mesh.cell_ptr[e]:mesh.cell_ptr[e + 1]].reshape(-1, mesh.dim)
+        d = np.sqrt(((v[:, None, :] - v[None, :, :]) ** 2).sum(-1)).max()
+        h = max(h, float(d))
+    return h
+
+
+def bench_table1(args):
+    """The paper's Table-1 experiment (Section 5) on the library: per fine mesh
+    N_h, degree p = q and coarse size H = k h, the mean PCG iterations per time
+    step and the Lanczos condition-number estimate of the last step's solve;
+    plus the unpreconditioned CG rows (B = I).  Prints one line per cell, a
+    markdown table beside the paper's numbers, and one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2512_19536_amd import _lib, from_problem, initial_state
+    from paper_2512_19536_amd._lib import PdgError
+    from pdg_inputs import problems
+
+    dev = "cuda:0"
+    with open(os.path.join(ROOT, "tests", "golden", "table1_paper.json")) as f:
+        paper = json.load(f)
+    ps = [int(v) for v in args.t1_p.split(",")]
+    nhs = [int(v) for v in args.t1_nh.split(",")]
+    ks = [int(v) for v in args.t1_h.split(",")]
+    cells, dofs_steps, solve_s = [], 0, 0.0
+
+    def run(pr, n_steps, precond):
+        nonlocal dofs_steps, solve_s
+        t0 = time.perf_counter()
+        stream = torch.cuda.Stream(device=dev)
+        opts = {_lib.PDG_OPT_GRAPH: 1, _lib.PDG_OPT_CHUNK: 16, _lib.PDG_OPT_LANCZOS_CAP: 1 << 15}
+        ctx = from_problem(pr, device=dev, options=opts, stream=stream)
+        if not precond:
+            ctx.set_option(_lib.PDG_OPT_PRECONDITIONER, 0)
+        t_setup = time.perf_counter() - t0
+        U, Up, Y = initial_state(ctx, pr)
+        torch.cuda.synchronize()
+        iters = []
+        t0 = time.perf_counter()
+        for k in range(n_steps):
+            info = ctx.step(U, Up, Y, None, pr.tol, 40000)
+            iters.append(info["iters"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kappa = ctx.lanczos()[0]
+        dofs_steps += pr.n_dof * n_steps
+        solve_s += dt
+        del ctx
+        torch.cuda.empty_cache()
+        return {"iters_mean": float(np.mean(iters)), "iters_first": iters[0], "iters_last": iters[-1],
+                "kappa_last_step": kappa, "ms_per_step": dt * 1e3 / n_steps, "setup_s": round(t_setup, 2)}
+
+    for p in ps:
+        for ci, nh in enumerate(nhs):
+            col = problems.TABLE1_NH.index(nh) if nh in problems.TABLE1_NH else None
+            h = None
+            for k in ks + [0]:
+                t0 = time.perf_counter()
+                pr = problems.table1_problem(nh, p, k if k else ks[-1], n_steps=args.t1_steps)
+                if h is None:
+                    h = _mesh_h(pr.mesh)
+                row = f"H={k}h" if k else "CG"
+                cell = {"p": p, "N_h": nh, "h": round(h, 4), "row": row, "n_dof": pr.n_dof,
+                        "n_coarse": int(pr.elem_coarse.max()) + 1 if k else 0,
+                        "coarse_dofs": (int(pr.elem_coarse.max()) + 1) * pr.nd if k else 0}
+                if col is not None and row in paper[f"p{p}"]:
+                    kp, ip = paper[f"p{p}"][row][col]
+                    cell["paper"] = {"kappa": kp, "iters": ip}
+                try:
+                    cell.update(run(pr, args.t1_steps if k else args.t1_cg_steps, precond=bool(k)))
+                except PdgError as e:
+                    cell["error"] = str(e)
+                cells.append(cell)
+                log(f"[table1] p={p} N_h={nh} {row}: " + json.dumps({kk: v for kk, v in cell.items()
+                                                                    if kk not in ("p", "N_h", "row")})
+                    + f" ({time.perf_counter() - t0:.1f} s)")
+    # markdown summary: ours (paper)
+    lines = []
+    for p in ps:
+        lines.append(f"p = q = {p}: kappa estimate / mean iterations per step, this library (paper)")
+        lines.append("| row | " + " | ".join(f"N_h={nh}" for nh in nhs) + " |")
+        lines.append("|---|" + "---|" * len(nhs))
+        for row in [f"H={k}h" for k in ks] + ["CG"]:
+            out = []
+            for nh in nhs:
+                c = next(c for c in cells if c["p"] == p and c["N_h"] == nh and c["row"] == row)
+                if "error" in c:
+                    out.append("n/a")
+                    continue
+                txt = f"{c['kappa_last_step']:.4g} / {c['iters_mean']:.1f}"
+                if "paper" in c:
+                    txt += f" ({c['paper']['kappa']:.4g} / {c['paper']['iters']})"
+                out.append(txt)
+            lines.append(f"| {row} | " + " | ".join(out) + " |")
+        lines.append("")
+    log("\n".join(lines))
+    if args.t1_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.t1_out)), exist_ok=True)
+        with open(args.t1_out, "w") as f:
+            json.dump({"cells": cells, "markdown": lines, "steps": args.t1_steps, "cg_steps": args.t1_cg_steps,
+                       "chi_cm": problems.TABLE1_CHI_CM}, f, indent=1)
+    out = {
+        "metric": "Table-1 experiment: mean PCG iterations per step and Lanczos kappa per (N_h, H, p) cell",
+        "value": round(dofs_steps / solve_s / 1e6, 3) if solve_s else None,
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": args.t1_steps,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"table1: 2-D grey/white square, N_h in {nhs}, p = q in {ps}, H = {ks} h, "
+                                f"one subdomain per element + q = p coarse, dt 2.5 us, relres 1e-9, "
+                                f"{args.t1_steps} steps per cell ({args.t1_cg_steps} for CG)")},
+        "cells": cells,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "table1"])
+    ap.add_argument("--t1-p", default="1,4", help="table1: degrees p = q")
+    ap.add_argument("--t1-nh", default="512,1024,2048,4096", help="table1: fine mesh sizes N_h")
+    ap.add_argument("--t1-h", default="2,4,8,16", help="table1: coarse sizes H / h")
+    ap.add_argument("--t1-steps", type=int, default=100, help="table1: time steps per preconditioned cell")
+    ap.add_argument("--t1-cg-steps", type=int, default=10, help="table1: time steps per unpreconditioned cell")
+    ap.add_argument("--t1-out", default=None, help="table1: JSON file for the cells")
     ap.add_argument("--epochs", type=int, default=30, help="cfg5: training epochs")
     ap.add_argument("--batch-steps", type=int, default=4, help="cfg5: time steps per training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="cfg5: peak learning rate")
@@ -354,6 +488,8 @@ def main():
         return bench_batch(args)
     if args.workload == "cfg5":
         return bench_learned(args)
+    if args.workload == "table1":
+        return bench_table1(args)
     if args.graph is None:
         args.graph = 0
 

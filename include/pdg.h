@@ -158,7 +158,8 @@ pdg_status pdg_set_ionic(pdg_ctx *ctx, const double *params, int32_t n_params);
  *   elem_sub    [n_elem] in 0..n_sub-1 (every subdomain non-empty)
  *   elem_coarse [n_elem] in 0..n_coarse-1, or NULL = the subdomains
  *   coarse_q    0 = one-level (no coarse correction), 1..p otherwise
- * Errors: PDG_EINVAL (labels, sizes, subdomain larger than 6144 dofs),
+ * Errors: PDG_EINVAL (labels, sizes, subdomain larger than 6144 dofs, coarse
+ *         system of one batch system larger than 16384 dofs),
  * PDG_ENOTSPD (a Cholesky pivot <= 0). */
 typedef struct {
     int32_t n_sub;
@@ -200,7 +201,14 @@ typedef enum {
     PDG_OPT_GRAPH = 5,          /* 1: replay each chunk of PCG iterations as a captured HIP graph
                                    (captured on first use; not while kernel timing is on);
                                    needs a non-NULL stream in pdg_create (else PDG_EINVAL) */
-    PDG_OPT_SPMV_WAVES = 6      /* wavefronts per SpMV block-row group: 1, 2, 4 (default) or 8 */
+    PDG_OPT_SPMV_WAVES = 6,     /* wavefronts per SpMV block-row group: 1, 2, 4 (default) or 8 */
+    PDG_OPT_PRECONDITIONER = 7, /* 1 (default): two-level additive Schwarz B_ad^{-1} of eq. (5);
+                                   0: none (B = I, plain CG), the reference rows of the paper's
+                                   Table 1.  pdg_precond_apply then copies r to z. */
+    PDG_OPT_LANCZOS_CAP = 8     /* PCG coefficients (alpha_j, beta_j) kept per system for
+                                   pdg_lanczos, 1..2^20 (default 2048; 16 bytes each per
+                                   system in the workspace).  Set before pdg_workspace_query /
+                                   pdg_bind_workspace. */
 } pdg_option;
 pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 
@@ -292,15 +300,16 @@ pdg_status pdg_get_system_info(const pdg_ctx *ctx, int32_t sys, pdg_solve_info *
  * tridiagonal Lanczos matrix built from the PCG coefficients,
  * T_11 = 1/alpha_1, T_jj = 1/alpha_j + beta_(j-1)/alpha_(j-1),
  * T_j,j+1 = sqrt(beta_j)/alpha_j, j = 1..iters).  The coefficients are kept
- * on the device during every solve (up to 2048 iterations); the eigenvalues
- * are found on the device by Sturm-count bisection.  kappa = lambda_max /
+ * on the device during every solve (up to PDG_OPT_LANCZOS_CAP iterations,
+ * default 2048; PDG_EINVAL when the solve took more); the eigenvalues are
+ * found on the device by Sturm-count bisection.  kappa = lambda_max /
  * lambda_min; any output may be NULL.  Call right after the solve (PDG_ESTATE
  * otherwise); synchronises the stream. */
 pdg_status pdg_lanczos(pdg_ctx *ctx, int32_t sys, double *kappa, double *lambda_min, double *lambda_max);
 
 /* Host copies of those PCG coefficients: alpha[j-1] = alpha_j (j = 1..m) and
  * beta[j-1] = beta_j = (r_j, z_j) / (r_(j-1), z_(j-1)), with
- * m = min(n, iterations of the last solve, 2048); beta_m of the converged
+ * m = min(n, iterations of the last solve, PDG_OPT_LANCZOS_CAP); beta_m of the converged
  * iteration is not used by the Lanczos matrix.  Either pointer may be NULL.
  * Call right after the solve (PDG_ESTATE otherwise); synchronises. */
 pdg_status pdg_get_pcg_coefficients(pdg_ctx *ctx, int32_t sys, double *alpha, double *beta, int32_t n);

@@ -108,6 +108,9 @@ struct pdg_ctx {
     int max_nj = 1;
     int64_t items_reserved = 0;
     int pre_pq = 0, pre_rz = 0;  // dot products pre-summed by the reduction kernel
+    int pre_rr = 0;              // same for (r, r) when no preconditioner is applied
+    bool no_precond = false;     // B = I: plain CG
+    int lcap = 2048;             // PCG coefficients kept per system (Lanczos estimate)
     bool lanczos_ok = false;     // device scalars still hold the last solve
     // group-ELL matrix (host staging)
     int G = 1;
@@ -178,7 +181,6 @@ constexpr int kOnePerWorkgroup = 1 << 30;
 // Above this many (consumer workgroup x partial) reads per system, a
 // dedicated reduction kernel sums the partials once instead.
 constexpr int64_t kRedundantReads = 1 << 22;
-constexpr int kLanczosCap = 2048;  // PCG coefficients kept per system for the Lanczos estimate
 
 // Splits each system's unit range [r_unit[s], r_unit[s+1]) into workgroups
 // of per_s = ceil(n_s / target) consecutive units; wg0 receives the first unit
@@ -298,7 +300,7 @@ void plan_chunks(pdg_ctx *c) {
 // partials, the p-update kernel's workgroups its Schwarz shares; where that
 // is many reads, the reduction kernel does it once.
 void choose_reductions(pdg_ctx *c) {
-    int64_t upd = 0, pup = 0;
+    int64_t upd = 0, pup = 0, pur = 0;
     const int nd = c->mesh.nd;
     for (int b = 0; b < c->n_sys; ++b) {
         const int64_t n_up = c->r_upd[b + 1] - c->r_upd[b], n_sp = c->r_spmv[b + 1] - c->r_spmv[b];
@@ -306,9 +308,11 @@ void choose_reductions(pdg_ctx *c) {
         const int64_t n_pu = (dofs + 255) / 256 + 1, n_sw = c->r_item[b + 1] - c->r_item[b];
         upd = std::max(upd, n_up * n_sp);
         pup = std::max(pup, n_pu * n_sw);
+        pur = std::max(pur, n_pu * n_up);
     }
     c->pre_pq = upd > kRedundantReads;
     c->pre_rz = pup > kRedundantReads;
+    c->pre_rr = pur > kRedundantReads;
 }
 
 size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32 ? 4 : 2); }
@@ -460,7 +464,7 @@ void plan_layout(pdg_ctx *c) {
     w.sca = L.add(n_sys * sizeof(DevScalars));
     w.part = L.add(std::max<int64_t>(1, (int64_t)c->spmv_wg_g0.size()) * 2 * 8);  // SpMV partials
     w.rrpart = L.add(std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8);     // update partials
-    w.lanc = L.add((size_t)n_sys * kLanczosCap * 16);                             // PCG coefficients
+    w.lanc = L.add((size_t)n_sys * c->lcap * 16);                                 // PCG coefficients
 }
 
 template <class T>
@@ -578,7 +582,7 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
     u.init = init;
     u.pre_pq = c->pre_pq;
     u.nd = c->mesh.nd;
-    u.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
+    u.nq0 = c->pc.q > 0 && !c->no_precond ? c->pc.nq0 : 0;
     u.grp_ptr = wptr<int32_t>(c, c->w.grpptr);
     u.grp_elems = wptr<int32_t>(c, c->w.grpel);
     u.grp_sys = wptr<int32_t>(c, c->w.upsys);
@@ -588,26 +592,28 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
     u.r = r;
     u.p = wptr<double>(c, c->w.p);
     u.q = wptr<double>(c, c->w.q);
-    u.P = c->pc.q > 0 ? wptr<double>(c, c->w.P) : nullptr;
+    u.P = u.nq0 > 0 ? wptr<double>(c, c->w.P) : nullptr;
     u.r0part = wptr<double>(c, c->w.r0p);
     u.pqpart = wptr<double>(c, c->w.part);
     u.rrpart = wptr<double>(c, c->w.rrpart);
     u.lanczos = sc == c->sc ? wptr<double2>(c, c->w.lanc) : nullptr;
-    u.lcap = kLanczosCap;
+    u.lcap = c->lcap;
     u.rng = ranges(c);
     u.sc = sc;
     return u;
 }
 
-PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
+// r: the residual the preconditioner acts on (read directly when B = I).
+PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, const double *r, DevScalars *sc) {
     PupdateArgs p{};
     p.mode = mode;
-    p.pre_rz = c->pre_rz;
+    p.pre_rz = c->no_precond ? c->pre_rr : c->pre_rz;
     p.nd = c->mesh.nd;
-    p.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
+    p.nq0 = c->pc.q > 0 && !c->no_precond ? c->pc.nq0 : 0;
+    p.r_ident = c->no_precond ? r : nullptr;
     p.n_elem = c->mesh.n_elem;
-    p.P = c->pc.q > 0 ? wptr<double>(c, c->w.P) : nullptr;
-    p.elem_coarse = c->pc.q > 0 ? wptr<int32_t>(c, c->w.ecoa) : nullptr;
+    p.P = p.nq0 > 0 ? wptr<double>(c, c->w.P) : nullptr;
+    p.elem_coarse = p.nq0 > 0 ? wptr<int32_t>(c, c->w.ecoa) : nullptr;
     p.elem_sys = wptr<int32_t>(c, c->w.elsys);
     p.dof_rt = wptr<int32_t>(c, c->w.dofrt);
     p.rt_item0 = wptr<int32_t>(c, c->w.rtit0);
@@ -625,12 +631,25 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, DevScalars *sc) {
     p.rng = ranges(c);
     p.p = out;
     p.lanczos = sc == c->sc ? wptr<double2>(c, c->w.lanc) : nullptr;
-    p.lcap = kLanczosCap;
+    p.lcap = c->lcap;
     p.sc = sc;
     return p;
 }
 
 double *vec(pdg_ctx *c, int item) { return wptr<double>(c, item); }
+
+// The Schwarz apply on the internal residual and the optional pre-summed
+// (r, z); with B = I only the pre-summed (r, r).
+void launch_precond(pdg_ctx *c, int mode, DevScalars *sc, bool timed) {
+    hipStream_t s = c->stream;
+    if (c->no_precond) {
+        if (c->pre_rr) HIPCHK(launch_reduce(wptr<double>(c, c->w.rrpart), wptr<int32_t>(c, c->w.rupd), c->n_sys, 1, sc, s));
+        return;
+    }
+    if (timed) launch_schwarz_timed(c, schwarz_args(c, mode, vec(c, c->w.r), sc));
+    else launch_schwarz_plain(c, schwarz_args(c, mode, vec(c, c->w.r), sc));
+    if (c->pre_rz) HIPCHK(launch_reduce(vec(c, c->w.itdot), wptr<int32_t>(c, c->w.ritem), c->n_sys, 1, sc, s));
+}
 
 // The four launches of one PCG iteration on the internal vectors (no
 // iteration index: the kernels take it from the device scalars).
@@ -645,11 +664,8 @@ void launch_iteration(pdg_ctx *c, bool timed) {
     HIPCHK(launch_spmv(c->dA, q, s));
     if (c->pre_pq) HIPCHK(launch_reduce(q.part, wptr<int32_t>(c, c->w.rspmv), c->n_sys, 0, c->sc, s));
     HIPCHK(launch_update(update_args(c, 0, vec(c, c->w.x), vec(c, c->w.r), c->sc), s));
-    if (timed) launch_schwarz_timed(c, schwarz_args(c, 2, vec(c, c->w.r), c->sc));
-    else launch_schwarz_plain(c, schwarz_args(c, 2, vec(c, c->w.r), c->sc));
-    if (c->pre_rz)
-        HIPCHK(launch_reduce(vec(c, c->w.itdot), wptr<int32_t>(c, c->w.ritem), c->n_sys, 1, c->sc, s));
-    HIPCHK(launch_pupdate(pupdate_args(c, 2, vec(c, c->w.p), c->sc), s));
+    launch_precond(c, 2, c->sc, timed);
+    HIPCHK(launch_pupdate(pupdate_args(c, 2, vec(c, c->w.p), vec(c, c->w.r), c->sc), s));
 }
 
 // Captures one chunk of iterations as a graph (once per chunk length).
@@ -750,9 +766,8 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
     }
     HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.x), vec(c, c->w.r), sc), s));
     c->ev_used = 0;
-    launch_schwarz_timed(c, schwarz_args(c, 1, vec(c, c->w.r), sc));
-    if (c->pre_rz) HIPCHK(launch_reduce(vec(c, c->w.itdot), wptr<int32_t>(c, c->w.ritem), c->n_sys, 1, sc, s));
-    HIPCHK(launch_pupdate(pupdate_args(c, 1, vec(c, c->w.p), sc), s));
+    launch_precond(c, 1, sc, true);
+    HIPCHK(launch_pupdate(pupdate_args(c, 1, vec(c, c->w.p), vec(c, c->w.r), sc), s));
     PcgRun &R = c->run;
     R = PcgRun();
     R.x = x;
@@ -1043,7 +1058,6 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
     return guard(c, [&] {
         require(c, S_ASSEMBLED, "pdg_setup_preconditioner");
         if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "preconditioner already set up");
-        if (d && d->coarse_q > 1) throw Error(PDG_EINVAL, "coarse_q must be 0 or 1");
         setup_precond(c->mesh, c->K, c->M, d, c->elem_sys, c->n_sys, c->pc, c->n_threads);
         build_group_ell(c);
         plan_chunks(c);
@@ -1284,6 +1298,16 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             c->dA.wpg = (int)value;
             drop_graph(c);
             break;
+        case PDG_OPT_LANCZOS_CAP:
+            if (value < 1 || value > (1 << 20)) throw Error(PDG_EINVAL, "Lanczos cap must be in 1..2^20");
+            if (c->state >= S_BOUND) throw Error(PDG_ESTATE, "set the Lanczos cap before pdg_bind_workspace");
+            c->lcap = (int)value;
+            break;
+        case PDG_OPT_PRECONDITIONER:
+            if (value != 0 && value != 1) throw Error(PDG_EINVAL, "preconditioner must be 0 (none) or 1 (Schwarz)");
+            c->no_precond = value == 0;
+            drop_graph(c);
+            break;
         default: throw Error(PDG_EINVAL, "unknown option");
         }
     });
@@ -1330,8 +1354,8 @@ pdg_status pdg_precond_apply(pdg_ctx *c, const double *r, double *z) {
         // restriction only (init mode: x and r untouched)
         HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.t), const_cast<double *>(r), sc), c->stream));
         c->ev_used = 0;
-        launch_schwarz_timed(c, schwarz_args(c, 0, r, sc));
-        HIPCHK(launch_pupdate(pupdate_args(c, 0, z, sc), c->stream));
+        if (!c->no_precond) launch_schwarz_timed(c, schwarz_args(c, 0, r, sc));
+        HIPCHK(launch_pupdate(pupdate_args(c, 0, z, r, sc), c->stream));
         if (c->timing) {
             HIPCHK(hipStreamSynchronize(c->stream));
             harvest_timing(c, 1);
@@ -1489,8 +1513,9 @@ pdg_status pdg_lanczos(pdg_ctx *c, int32_t sys, double *kappa, double *lambda_mi
         require_gpu(c);
         if (sys < 0 || sys >= c->n_sys) throw Error(PDG_EINVAL, "system index out of range");
         if (!c->lanczos_ok) throw Error(PDG_ESTATE, "pdg_lanczos: call right after pdg_solve / pdg_step");
-        if (c->last[sys].iters > kLanczosCap) throw Error(PDG_EINVAL, "more iterations than coefficients kept (2048)");
-        HIPCHK(launch_lanczos(wptr<double2>(c, c->w.lanc), kLanczosCap, c->n_sys, c->sc, c->stream));
+        if (c->last[sys].iters > c->lcap)
+            throw Error(PDG_EINVAL, "more iterations than coefficients kept (raise PDG_OPT_LANCZOS_CAP)");
+        HIPCHK(launch_lanczos(wptr<double2>(c, c->w.lanc), c->lcap, c->n_sys, c->sc, c->stream));
         HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, c->n_sys * sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         const DevScalars &h = c->sc_host[sys];
@@ -1505,10 +1530,10 @@ pdg_status pdg_get_pcg_coefficients(pdg_ctx *c, int32_t sys, double *alpha, doub
         require_gpu(c);
         if (sys < 0 || sys >= c->n_sys || n < 0) throw Error(PDG_EINVAL, "bad arguments");
         if (!c->lanczos_ok) throw Error(PDG_ESTATE, "pdg_get_pcg_coefficients: call right after pdg_solve / pdg_step");
-        const int m = std::min({n, c->last[sys].iters, kLanczosCap});
+        const int m = std::min({n, c->last[sys].iters, c->lcap});
         std::vector<double> h(2 * (size_t)std::max(m, 1));
         if (m > 0)
-            HIPCHK(hipMemcpyAsync(h.data(), wptr<double2>(c, c->w.lanc) + (size_t)sys * kLanczosCap, m * 16,
+            HIPCHK(hipMemcpyAsync(h.data(), wptr<double2>(c, c->w.lanc) + (size_t)sys * c->lcap, m * 16,
                                   hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         for (int j = 0; j < m; ++j) {

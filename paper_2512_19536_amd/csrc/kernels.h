@@ -133,6 +133,7 @@ struct PupdateArgs {
     int mode;               // 0: out = z; 1: PCG init, p = z; 2: PCG, p = z + beta p
     int pre_rz;             // 1: take (r, z) from sc.rz_sum instead of summing the Schwarz shares
     int nd, nq0;
+    const double *r_ident;  // non-null: no preconditioner (z = r_ident, (r, z) from the update partials)
     int64_t n_elem;
     const double *P;
     const int32_t *elem_coarse;  // coarse element of each element (system-contiguous numbering)

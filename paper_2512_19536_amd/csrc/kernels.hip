@@ -591,9 +591,11 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
             DevScalars *sc = a.sc + b;
             // the owner block may set `done` during this launch
             if (block_bcast<256>(threadIdx.x == 0 ? sc->done : 0)) continue;
-            const int it0 = a.rng.item[b];
+            const int it0 = a.r_ident ? a.rng.upd[b] : a.rng.item[b];
+            const int it1 = a.r_ident ? a.rng.upd[b + 1] : a.rng.item[b + 1];
             const double rz = a.pre_rz ? sc->rz_sum
-                                       : block_sum_partials<256>(a.itemdot + it0, a.rng.item[b + 1] - it0, 1, 0);
+                                       : block_sum_partials<256>(a.r_ident ? a.rrpart + it0 : a.itemdot + it0,
+                                                                 it1 - it0, 1, 0);
             const int j = a.mode == 2 ? sc->jcur : 0;
             const double bt = a.mode == 2 ? rz / sc->rz[(j - 1) & 1] : 0.0;
             if (my == b) {
@@ -656,18 +658,23 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
         const int bad = __syncthreads_or(ce < c_lo || ce >= c_lo + n_c);
         if (bad || n_c > KMAX || n_c < 1) n_c = KMAX + 1;
         if (n_c <= KMAX) {
-            if ((int)threadIdx.x < n_c * NQ) {
-                const int c = c_lo + (int)threadIdx.x / NQ, j = (int)threadIdx.x % NQ;
+            for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
+                const int c = c_lo + t / NQ, j = t % NQ;
                 const int b = a.coarse_sys[c];
                 const int gi = (c - a.csys_ce0[b]) * NQ + j;
-                s_z0[threadIdx.x] = tile_row_value(a, a.coarse_rt0[b] + (gi >> 6), gi & 63);
+                s_z0[t] = tile_row_value(a, a.coarse_rt0[b] + (gi >> 6), gi & 63);
             }
             __syncthreads();
         }
     }
     if (!active) return;
-    const int dr = a.dof_rt[idx];
-    double zz = tile_row_value(a, dr >> 6, dr & 63);
+    double zz;
+    if (a.r_ident) {
+        zz = a.r_ident[idx];
+    } else {
+        const int dr = a.dof_rt[idx];
+        zz = tile_row_value(a, dr >> 6, dr & 63);
+    }
     if (NQ > 0) {
         const int64_t e = idx / nd;
         const int ce = a.elem_coarse[e];
@@ -705,78 +712,112 @@ __global__ __launch_bounds__(BS) void k_reduce(const double *part, const int32_t
     }
 }
 
+// Entries of the Lanczos tridiagonal matrix T_m from the PCG coefficients
+// h[j] = (alpha_j, beta_j): T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+// T_{j,j+1}^2 = beta_j / alpha_j^2 (formed as (sqrt(beta_j)/alpha_j)^2).
+__device__ inline double lanczos_diag(const double2 *h, int j) {
+    return 1.0 / h[j].x + (j > 0 ? h[j - 1].y / h[j - 1].x : 0.0);
+}
+__device__ inline double lanczos_off2(const double2 *h, int j) {
+    const double off = sqrt(h[j].y) / h[j].x;
+    return off * off;
+}
+
+// T_m held in LDS (short histories) ...
+struct TriLds {
+    const double *d, *e2;
+    __device__ double diag(int j) const { return d[j]; }
+    __device__ double off2(int j) const { return e2[j]; }
+};
+// ... or formed on the fly from the history in global memory (long ones);
+// both give the same values.
+struct TriHist {
+    const double2 *h;
+    __device__ double diag(int j) const { return lanczos_diag(h, j); }
+    __device__ double off2(int j) const { return lanczos_off2(h, j); }
+};
+
 // Number of eigenvalues below x of the symmetric tridiagonal matrix with
-// diagonal d and off-diagonal e (Sturm sequence of the LDL^T pivots).
-__device__ inline int sturm_count(const double *d, const double *e2, int m, double x, double tiny) {
+// diagonal d and squared off-diagonal e2 (Sturm sequence of the LDL^T pivots).
+template <typename Tri>
+__device__ inline int sturm_count(const Tri &T, int m, double x, double tiny) {
     int c = 0;
-    double q = d[0] - x;
+    double q = T.diag(0) - x;
     for (int j = 0;;) {
         if (q < 0.0) ++c;
         if (++j >= m) break;
         if (fabs(q) < tiny) q = q < 0.0 ? -tiny : tiny;
-        q = d[j] - x - e2[j - 1] / q;
+        q = T.diag(j) - x - T.off2(j - 1) / q;
     }
     return c;
 }
 
 // Extreme eigenvalues by parallel bisection: each round the 256 threads count
 // at 256 interior points of the bracket, which shrinks 257-fold.
-__global__ __launch_bounds__(256) void k_lanczos(const double2 *hist, int lcap, DevScalars *sc) {
-    constexpr int NT = 256, MAXM = 2048;
-    __shared__ double d[MAXM], e2[MAXM];
-    __shared__ int s_cnt[NT];
-    __shared__ double s_lo, s_hi;
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int m = min(min(sc[b].iters, lcap), MAXM);
-    if (m < 1) {
-        if (t == 0) sc[b].lmin = sc[b].lmax = 1.0;
-        return;
-    }
-    const double2 *h = hist + (int64_t)b * lcap;
-    for (int j = t; j < m; j += NT) {
-        d[j] = 1.0 / h[j].x + (j > 0 ? h[j - 1].y / h[j - 1].x : 0.0);
-        if (j + 1 < m) {
-            const double off = sqrt(h[j].y) / h[j].x;
-            e2[j] = off * off;
-        }
-    }
-    __syncthreads();
+template <typename Tri>
+__device__ void lanczos_extremes(const Tri &T, int m, DevScalars *sc, int *s_cnt, double *s_lohi) {
+    constexpr int NT = 256;
+    const int t = threadIdx.x;
     if (t == 0) {  // Gershgorin bracket
         double lo = 1e300, hi = -1e300;
         for (int j = 0; j < m; ++j) {
-            const double r = (j > 0 ? sqrt(e2[j - 1]) : 0.0) + (j + 1 < m ? sqrt(e2[j]) : 0.0);
-            lo = fmin(lo, d[j] - r);
-            hi = fmax(hi, d[j] + r);
+            const double r = (j > 0 ? sqrt(T.off2(j - 1)) : 0.0) + (j + 1 < m ? sqrt(T.off2(j)) : 0.0);
+            lo = fmin(lo, T.diag(j) - r);
+            hi = fmax(hi, T.diag(j) + r);
         }
-        s_lo = lo;
-        s_hi = hi;
+        s_lohi[0] = lo;
+        s_lohi[1] = hi;
     }
     __syncthreads();
-    const double glo = s_lo, ghi = s_hi;
+    const double glo = s_lohi[0], ghi = s_lohi[1];
     const double tiny = 1e-300 + 1e-30 * fmax(fabs(glo), fabs(ghi));
     for (int which = 0; which < 2; ++which) {  // 0: smallest (count >= 1), 1: largest (count >= m)
         const int target = which == 0 ? 1 : m;
         double lo = glo, hi = ghi;
         for (int round = 0; round < 8; ++round) {
             const double x = lo + (hi - lo) * (double)(t + 1) / (double)(NT + 1);
-            s_cnt[t] = sturm_count(d, e2, m, x, tiny) >= target;
+            s_cnt[t] = sturm_count(T, m, x, tiny) >= target;
             __syncthreads();
             if (t == 0) {
                 int k = 0;
                 while (k < NT && !s_cnt[k]) ++k;  // first point whose count reaches the target
                 const double w = (hi - lo) / (double)(NT + 1);
-                s_hi = k < NT ? lo + w * (k + 1) : hi;
-                s_lo = lo + w * k;
+                s_lohi[1] = k < NT ? lo + w * (k + 1) : hi;
+                s_lohi[0] = lo + w * k;
             }
             __syncthreads();
-            lo = s_lo;
-            hi = s_hi;
+            lo = s_lohi[0];
+            hi = s_lohi[1];
             __syncthreads();
         }
         if (t == 0) {
-            if (which == 0) sc[b].lmin = 0.5 * (lo + hi);
-            else sc[b].lmax = 0.5 * (lo + hi);
+            if (which == 0) sc->lmin = 0.5 * (lo + hi);
+            else sc->lmax = 0.5 * (lo + hi);
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lanczos(const double2 *hist, int lcap, DevScalars *sc) {
+    constexpr int NT = 256, MAXM = 2048;
+    __shared__ double d[MAXM], e2[MAXM];
+    __shared__ int s_cnt[NT];
+    __shared__ double s_lohi[2];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int m = min(sc[b].iters, lcap);
+    if (m < 1) {
+        if (t == 0) sc[b].lmin = sc[b].lmax = 1.0;
+        return;
+    }
+    const double2 *h = hist + (int64_t)b * lcap;
+    if (m <= MAXM) {
+        for (int j = t; j < m; j += NT) {
+            d[j] = lanczos_diag(h, j);
+            if (j + 1 < m) e2[j] = lanczos_off2(h, j);
+        }
+        __syncthreads();
+        lanczos_extremes(TriLds{d, e2}, m, sc + b, s_cnt, s_lohi);
+    } else {
+        lanczos_extremes(TriHist{h}, m, sc + b, s_cnt, s_lohi);
     }
 }
 
@@ -1107,12 +1148,19 @@ hipError_t launch_spmv(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// nq0 = dim P^q of the coarse space: 3, 6, 10, 15 (2-D) or 4, 10, 20, 35 (3-D), 0 without
 template <int ND>
 static hipError_t update_nd(const UpdateArgs &a, hipStream_t s) {
+    const dim3 g(a.n_wg), b(128);
     switch (a.nq0) {
-    case 0: hipLaunchKernelGGL((k_update<ND, 0>), dim3(a.n_wg), dim3(128), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_update<ND, 3>), dim3(a.n_wg), dim3(128), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_update<ND, 4>), dim3(a.n_wg), dim3(128), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_update<ND, 0>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_update<ND, 3>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_update<ND, 4>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_update<ND, 6>), g, b, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_update<ND, 10>), g, b, 0, s, a); break;
+    case 15: hipLaunchKernelGGL((k_update<ND, 15>), g, b, 0, s, a); break;
+    case 20: hipLaunchKernelGGL((k_update<ND, 20>), g, b, 0, s, a); break;
+    case 35: hipLaunchKernelGGL((k_update<ND, 35>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1198,11 +1246,16 @@ hipError_t launch_schwarz(const SchwarzArgs &a, int grid, int local_store, int c
 hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s) {
     const int64_t n = a.n_elem * a.nd;
     if (n <= 0) return hipSuccess;
-    const int blocks = (int)((n + 255) / 256);
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
     switch (a.nq0) {
-    case 0: hipLaunchKernelGGL((k_pupdate<0>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pupdate<3>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pupdate<4>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_pupdate<0>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pupdate<3>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pupdate<4>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_pupdate<6>), g, b, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_pupdate<10>), g, b, 0, s, a); break;
+    case 15: hipLaunchKernelGGL((k_pupdate<15>), g, b, 0, s, a); break;
+    case 20: hipLaunchKernelGGL((k_pupdate<20>), g, b, 0, s, a); break;
+    case 35: hipLaunchKernelGGL((k_pupdate<35>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -18,7 +18,8 @@ struct Error : std::runtime_error {
 };
 
 constexpr int kTile = 64;           // dense inverse tile edge
-constexpr int kMaxLocalDofs = 6144; // largest subdomain handled by the Schwarz kernel
+constexpr int kMaxLocalDofs = 6144;   // largest subdomain (dense inverse per subdomain)
+constexpr int kMaxCoarseDofs = 16384; // largest coarse system per batch system (dense inverse, 2 GiB)
 constexpr int kIonicParams = 24;
 constexpr int kStates = 5;
 
@@ -60,7 +61,7 @@ void element_inverse(int n, const double *A, double *Ainv);  // small SPD invers
 
 // ---- dense SPD inversion and Schwarz setup (schwarz_setup.cpp) -------------
 // In-place inverse of a dense SPD matrix (row-major n x n).  Throws ENOTSPD.
-void spd_inverse(int64_t n, double *A);
+void spd_inverse(int64_t n, double *A, int n_threads = 1);
 
 struct DenseSys {
     int64_t n = 0;          // true size

@@ -56,28 +56,38 @@ static inline double dot(const double *a, const double *b, int64_t n) {
     return (s0 + s1) + (s2 + s3);
 }
 
-// A (row-major, SPD) -> A^{-1}.  Row-oriented Cholesky A = L L^T, then the
-// rows of W^T = (L^{-1})^T by forward substitution, then A^{-1} = W^T W.
-void spd_inverse(int64_t n, double *A) {
+// A (row-major, SPD) -> A^{-1}.  Cholesky A = L L^T column by column (the
+// entries below each pivot are independent), then the rows of
+// W^T = (L^{-1})^T by forward substitution (independent per row), then
+// A^{-1} = W^T W (independent per row).  With n_threads > 1 the independent
+// parts run on that many threads; every entry is formed by the same
+// expression in the same order either way, so the result does not depend on
+// the thread count.
+void spd_inverse(int64_t n, double *A, int n_threads) {
     std::vector<double> L(n * n, 0.0);
-    for (int64_t i = 0; i < n; ++i) {
-        double *Li = &L[i * n];
-        for (int64_t j = 0; j <= i; ++j) {
-            const double *Lj = &L[j * n];
-            double s = A[i * n + j] - dot(Li, Lj, j);
-            if (i == j) {
-                if (!(s > 0.0) || !std::isfinite(s))
-                    throw Error(PDG_ENOTSPD, "Cholesky pivot <= 0 (matrix not SPD)");
-                Li[i] = std::sqrt(s);
-            } else {
-                Li[j] = s / Lj[j];
-            }
+    const bool par = n_threads > 1 && n >= 256;
+    for (int64_t j = 0; j < n; ++j) {
+        double *Lj = &L[j * n];
+        const double s = A[j * n + j] - dot(Lj, Lj, j);
+        if (!(s > 0.0) || !std::isfinite(s)) throw Error(PDG_ENOTSPD, "Cholesky pivot <= 0 (matrix not SPD)");
+        Lj[j] = std::sqrt(s);
+        auto below = [&](int64_t i) {
+            double *Li = &L[i * n];
+            Li[j] = (A[i * n + j] - dot(Li, Lj, j)) / Lj[j];
+        };
+        const int64_t rows = n - j - 1;
+        if (par && rows * j >= (1 << 16)) {
+            const int64_t blk = 16, nb = (rows + blk - 1) / blk;
+            parallel_for(nb, [&](int64_t b) {
+                for (int64_t i = j + 1 + b * blk; i < std::min(n, j + 1 + (b + 1) * blk); ++i) below(i);
+            }, n_threads);
+        } else {
+            for (int64_t i = j + 1; i < n; ++i) below(i);
         }
     }
     // Wt[j][k] = (L^{-1})[k][j], k >= j: solve L w = e_j
     std::vector<double> Wt(n * n, 0.0);
-    std::vector<double> w(n);
-    for (int64_t j = 0; j < n; ++j) {
+    auto wrow = [&](int64_t j, std::vector<double> &w) {
         std::fill(w.begin(), w.end(), 0.0);
         w[j] = 1.0 / L[j * n + j];
         for (int64_t k = j + 1; k < n; ++k) {
@@ -85,14 +95,27 @@ void spd_inverse(int64_t n, double *A) {
             w[k] = -dot(Lk + j, &w[j], k - j) / Lk[k];
         }
         std::copy(w.begin() + j, w.end(), &Wt[j * n + j]);
-    }
+    };
     // A^{-1}[i][j] = sum_{k >= max(i,j)} Wt[i][k] Wt[j][k]
-    for (int64_t i = 0; i < n; ++i)
+    auto prow = [&](int64_t i) {
         for (int64_t j = 0; j <= i; ++j) {
             double s = dot(&Wt[i * n + i], &Wt[j * n + i], n - i);
             A[i * n + j] = s;
             A[j * n + i] = s;
         }
+    };
+    if (par) {
+        parallel_for(n, [&](int64_t j) {
+            thread_local std::vector<double> w;
+            w.resize(n);
+            wrow(j, w);
+        }, n_threads);
+        parallel_for(n, prow, n_threads);
+    } else {
+        std::vector<double> w(n);
+        for (int64_t j = 0; j < n; ++j) wrow(j, w);
+        for (int64_t i = 0; i < n; ++i) prow(i);
+    }
 }
 
 static void store_tiles(const double *D, int64_t n, double *tiles) {
@@ -265,7 +288,7 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
         pc.K0blk.assign(n_bsys, {});
         for (int b = 0; b < n_bsys; ++b) {
             const int64_t n0 = (int64_t)(pc.csys_ce0[b + 1] - pc.csys_ce0[b]) * nq0;
-            if (n0 > kMaxLocalDofs) throw Error(PDG_EINVAL, "coarse system exceeds 6144 dofs");
+            if (n0 > kMaxCoarseDofs) throw Error(PDG_EINVAL, "coarse system exceeds 16384 dofs");
             pc.K0blk[b].assign(n0 * n0, 0.0);
         }
         std::vector<double> KP(nd * nq0);
@@ -330,13 +353,21 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
         spd_inverse(ni, D.data());
         store_tiles(D.data(), ni, &pc.inv64[pc.sys[s].tile_off * kTile * kTile]);
     }, n_threads);
-    if (coarse)
-        parallel_for(n_bsys, [&](int64_t b) {
+    if (coarse) {
+        // few coarse systems: threads inside each inverse; many: one each
+        const int nt = n_threads <= 0 ? (int)std::max(1u, std::thread::hardware_concurrency()) : n_threads;
+        const bool inner = n_bsys < nt;
+        auto one = [&](int64_t b) {
             std::vector<double> D = pc.K0blk[b];
             const DenseSys &S = pc.sys[pc.n_sub + b];
-            spd_inverse(S.n, D.data());
+            spd_inverse(S.n, D.data(), inner ? nt : 1);
             store_tiles(D.data(), S.n, &pc.inv64[S.tile_off * kTile * kTile]);
-        }, n_threads);
+        };
+        if (inner)
+            for (int b = 0; b < n_bsys; ++b) one(b);
+        else
+            parallel_for(n_bsys, one, n_threads);
+    }
 }
 
 }  // namespace pdg

@@ -66,31 +66,45 @@ def _dedup(poly, labels, tol=1e-13):
 def voronoi_cells(points, n_cand=48):
     """Clipped Voronoi cells of ``points`` in [0,1]^2.
 
-    Returns a list of (vertices[m,2] counter-clockwise, edge_labels[m]) where a
-    label j >= 0 is the neighbouring seed and -1..-4 are the square's sides.
+    Each cell is the square clipped by the bisector half-planes of its nearest
+    seeds (nearest first); the candidate set grows until every seed left out
+    is provably too far to cut the cell (farther than twice the cell's
+    radius).  Returns a list of (vertices[m,2] counter-clockwise,
+    edge_labels[m]) where a label j >= 0 is the neighbouring seed and
+    -1..-4 are the square's sides.
     """
+    from scipy.spatial import cKDTree
+
+    points = np.asarray(points, dtype=np.float64)
     n = len(points)
     square = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
     sq_labels = [-1, -2, -3, -4]  # bottom, right, top, left
-    d2 = ((points[:, None, :] - points[None, :, :]) ** 2).sum(-1)
-    order = np.argsort(d2, axis=1)
+    tree = cKDTree(points)
     cells = []
     for i in range(n):
-        poly, labels = square.copy(), list(sq_labels)
-        for j in order[i, 1:min(n, n_cand + 1)]:
-            a = points[j] - points[i]
-            b = 0.5 * (points[j] @ points[j] - points[i] @ points[i])
-            # skip half-planes that cannot cut the current cell
-            if np.max(poly @ a - b) <= 0.0:
-                continue
-            poly, labels = _clip(poly, labels, a, b, int(j))
-        poly, labels = _dedup(poly, labels)
-        # every seed left out of the candidate set must be too far to cut the cell
-        if n > n_cand + 1:
+        nc = n_cand
+        while True:
+            k = min(n, nc + 2)
+            dist, idx = tree.query(points[i], k=k)
+            order = idx[np.argsort(dist, kind="stable")]
+            order = order[order != i]
+            use = order if k >= n else order[:nc]
+            poly, labels = square.copy(), list(sq_labels)
+            for j in use:
+                a = points[j] - points[i]
+                b = 0.5 * (points[j] @ points[j] - points[i] @ points[i])
+                # skip half-planes that cannot cut the current cell
+                if np.max(poly @ a - b) <= 0.0:
+                    continue
+                poly, labels = _clip(poly, labels, a, b, int(j))
+            poly, labels = _dedup(poly, labels)
+            if k >= n:
+                break
+            # every seed left out must be too far to cut the cell
             rmax = np.sqrt(((poly - points[i]) ** 2).sum(1).max())
-            far = d2[i, order[i, n_cand + 1]]
-            if far <= (2.0 * rmax) ** 2:
-                raise RuntimeError("voronoi_cells: candidate set too small")
+            if ((points[order[nc]] - points[i]) ** 2).sum() > (2.0 * rmax) ** 2:
+                break
+            nc *= 2
         cells.append((poly, labels))
     return cells
 

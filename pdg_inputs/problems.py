@@ -37,9 +37,13 @@ Workloads
           across it (grey: sigma0, isotropic); FP32 Schwarz solves.  Training
           seeds 100..119, held-out seeds 200..204, 100 steps each.
 ``small3d`` a tiny 3-D problem (6^3 cubes) for quick tests.
+``table1_problem(N_h, p, k)`` one cell of the paper's Table 1 (2-D grey/white
+          square, one subdomain per element, coarse degree q = p on
+          agglomerates of about k^2 elements, i.e. H = k h).
 """
 from __future__ import annotations
 
+import functools
 from dataclasses import dataclass, field, replace
 
 import numpy as np
@@ -247,6 +251,50 @@ def learned_small(n_grid=12, p=2, n_sub=8, seed=31) -> Problem:
     return _cube_problem(f"learned_small_{n_grid}", n_grid, 0.25 * n_grid, seed_mesh=seed, seed_part=seed + 1,
                          n_sub=n_sub, p=p, spread=0.3, sigma_kind="two_region", n_steps=40,
                          sigma0=SIGMA_3D, dt=DT_3D)
+
+
+# Table 1 of the paper (Section 5): 2-D square, grey matter on top (sigma = 0.63,
+# isotropic), white matter below (sigma_l = 0.69, sigma_n = 2.571 with the
+# anisotropy along the vertical), initial potential -50 mV in the disk
+# (x - 0.5)^2 + (y - 1)^2 < 0.016 and -67 mV elsewhere, dt = 2.5 us, one
+# element per subdomain, coarse space of degree q = p on agglomerates with
+# H = 2h .. 16h, stopping tolerance 1e-9.  chi_m C_m is not given; TABLE1_CHI_CM
+# is the value for which the condition number of the unpreconditioned system
+# at p = 1, N_h = 512 equals the paper's 1.34e4 (dense eigenvalues of that
+# matrix), used for every cell.
+TABLE1_CHI_CM = 0.014319
+TABLE1_NH = (512, 1024, 2048, 4096)
+TABLE1_H = (2, 4, 8, 16)
+
+
+@functools.lru_cache(maxsize=8)
+def _table1_mesh(n_h, seed):
+    return voronoi_mesh(n_h, seed=seed, lloyd=10)
+
+
+def table1_problem(n_h, p, h_ratio, chi_cm=None, seed=None, n_steps=10) -> Problem:
+    """One cell of Table 1: N_h Voronoi cells, degree p, coarse agglomerates of
+    about h_ratio^2 cells (H = h_ratio h), one subdomain per element."""
+    mesh = replace(_table1_mesh(n_h, 1000 + n_h if seed is None else seed))
+    n = mesh.n_elem
+    cen = mesh.element_centroid()
+    region = (cen[:, 1] < 0.5).astype(np.int32)  # 1 = white matter (bottom)
+    mesh.region = region
+    sig = isotropic_sigma(n, 2, 0.63)
+    sig[region == 1] = np.diag([0.69, 2.571])
+    mesh.sigma = sig
+    u0 = np.full(n, -67.0)
+    u0[(cen[:, 0] - 0.5) ** 2 + (cen[:, 1] - 1.0) ** 2 < 0.016] = -50.0
+    n_coarse = max(1, int(round(n_h / h_ratio ** 2)))
+    coarse = rcb(cen, n_coarse, region=region, spread=0.0, seed=n_h + h_ratio)
+    # number the elements agglomerate by agglomerate (the numbering is free)
+    perm = order_by_part(coarse, cen)
+    mesh = renumber_elements(mesh, perm)
+    coarse, u0 = coarse[perm], u0[perm]
+    chi = TABLE1_CHI_CM if chi_cm is None else chi_cm
+    return Problem(f"table1_N{n_h}_p{p}_H{h_ratio}h", mesh, p=p, chi_m=chi, c_m=1.0, dt=0.0025, eta0=10.0,
+                   elem_sub=np.arange(n, dtype=np.int32), elem_coarse=coarse.astype(np.int32), coarse_q=p,
+                   n_steps=n_steps, tol=1e-9, u0_elem=u0, y0_elem=_rest_state(n))
 
 
 CFG5_TRAIN_SEEDS = tuple(range(100, 120))

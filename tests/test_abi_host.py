@@ -2,6 +2,7 @@
 against the oracle (independent implementations), and error codes."""
 import os
 import re
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -44,6 +45,9 @@ CASES = {
     "2d_p4": lambda: problems.small2d(n=20, p=4),
     "3d_p1": lambda: problems.small3d(p=1),
     "3d_p3": lambda: problems.small3d(p=3),
+    "3d_p2_q2": lambda: replace(problems.small3d(p=2), coarse_q=2),
+    "t1_p2": lambda: problems.table1_problem(48, 2, 2),
+    "t1_p4": lambda: problems.table1_problem(40, 4, 2),
 }
 
 

@@ -8,6 +8,8 @@ the smaller count is within 1.2x the stopping threshold: late PCG residual
 norms move by 6-14 % under relative perturbations of b of 1e-15..1e-11 in the
 oracle itself, so such a count is decided by rounding.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -16,6 +18,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from oracle.monodomain import Monodomain  # noqa: E402
+from oracle.pcg import lanczos_kappa  # noqa: E402
 from paper_2512_19536_amd import _lib, solver  # noqa: E402
 from paper_2512_19536_amd._lib import PdgError  # noqa: E402
 from pdg_inputs import problems  # noqa: E402
@@ -42,6 +45,14 @@ CASES = {
     "3d_p2": lambda: problems.small3d(n_grid=8, p=2, n_sub=6),
     "3d_p3": lambda: problems.small3d(n_grid=8, p=3, n_sub=6),
     "3d_p4": lambda: problems.small3d(n_grid=6, p=4, n_sub=3),
+    # coarse degree q = p (Section 4: V_0 = P^q on the agglomerates, q <= p)
+    "3d_p2_q2": lambda: replace(problems.small3d(n_grid=8, p=2, n_sub=6), coarse_q=2),
+    # the Table-1 mode: one subdomain per element (block Jacobi) plus a
+    # q = p coarse space on agglomerates of ~4 elements (H = 2h); 375 coarse
+    # dofs for p = 4 span six tiles
+    "t1_p1": lambda: problems.table1_problem(64, 1, 2),
+    "t1_p3": lambda: problems.table1_problem(80, 3, 2),
+    "t1_p4": lambda: problems.table1_problem(100, 4, 2),
 }
 
 _cache = {}
@@ -52,7 +63,7 @@ def _setup(case):
         print(f"[setup] {case}", flush=True)
         pr = CASES[case]()
         md = Monodomain(pr)
-        ctx = solver.from_problem(pr, device=DEV)
+        ctx = solver.from_problem(pr, device=DEV, options={_lib.PDG_OPT_LANCZOS_CAP: 1 << 15})
         _cache[case] = (pr, md, ctx)
     return _cache[case]
 
@@ -143,7 +154,7 @@ def test_solve(case):
     assert info["relres"] <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["cfg1", "3d_p2", "3d_p3"])
+@pytest.mark.parametrize("case", ["cfg1", "3d_p2", "3d_p3", "t1_p3"])
 def test_time_steps(case):
     pr, md, ctx = _setup(case)
     nsteps = pr.n_steps if case == "cfg1" else 3
@@ -206,3 +217,43 @@ def test_reduced_precision_schwarz_still_meets_fp64_tolerance(prec):
     assert info["true_relres"] < 2e-10
     assert rel_l2(N(x), xo) < 1e-8
     assert info["iters"] <= oinfo.iters + 5
+
+
+@pytest.mark.parametrize("case", ["2d_p3", "t1_p1", "t1_p4"])
+def test_unpreconditioned_cg(case):
+    """B = I (the CG reference rows of Table 1): z = r exactly; a CG solve
+    meets the tolerance, lies within kappa * tol of the direct solution (the
+    bound for any iterate with that residual), takes the oracle's number of
+    iterations up to 2 % (CG run past n iterations in floating point, as here,
+    loses orthogonality at a rate set by rounding, so the count is not fixed
+    by the arithmetic alone), and its recorded (alpha, beta) give the oracle's
+    Lanczos kappa (t1_p4 takes ~2900 iterations: the long-history path).
+    Switching the preconditioner back on gives the bits of the earlier
+    preconditioned solve."""
+    pr, md, ctx = _setup(case)
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal(pr.n_dof)
+    x0 = rng.standard_normal(pr.n_dof)
+    xp_before = T(x0)
+    ctx.solve(T(b), xp_before, 1e-10, 2000)
+    ctx.set_option(_lib.PDG_OPT_PRECONDITIONER, 0)
+    try:
+        z = torch.empty(pr.n_dof, dtype=torch.float64, device=DEV)
+        ctx.precond_apply(T(b), z)
+        assert np.array_equal(N(z), b)
+        xo, oinfo = md.solve(b, x0, tol=1e-10, maxit=20000, precond=False)
+        x = T(x0)
+        info = ctx.solve(T(b), x, 1e-10, 20000)
+        kappa, _, _ = ctx.lanczos()
+        k_o = lanczos_kappa(oinfo.alphas, oinfo.betas)
+        print(case, "CG iters gpu", info["iters"], "oracle", oinfo.iters, "kappa", kappa, k_o, flush=True)
+        assert abs(info["iters"] - oinfo.iters) <= max(1, 0.02 * oinfo.iters)
+        assert info["relres"] <= 1e-10
+        xd = np.linalg.solve(md.K.toarray(), b)
+        assert rel_l2(N(x), xd) <= 2.0 * k_o * 1e-10
+        assert abs(kappa - k_o) <= 1e-3 * k_o
+    finally:
+        ctx.set_option(_lib.PDG_OPT_PRECONDITIONER, 1)
+    xp_after = T(x0)
+    ctx.solve(T(b), xp_after, 1e-10, 2000)
+    assert np.array_equal(N(xp_after), N(xp_before))

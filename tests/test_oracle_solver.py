@@ -15,7 +15,7 @@ from oracle.assemble import evaluate
 from oracle.basis import eval_basis
 from oracle.monodomain import Monodomain
 from oracle.pcg import lanczos_kappa, pcg
-from oracle.schwarz import Schwarz
+from oracle.schwarz import Schwarz, coarse_prolongation
 from pdg_inputs import params, problems
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -97,10 +97,12 @@ def test_schwarz_symmetric_positive_definite(small2d):
         np.testing.assert_allclose(L @ L.T, K[np.ix_(d, d)], rtol=0, atol=1e-11 * abs(K).max())
 
 
-def test_coarse_transfer_reproduces_coarse_basis(small2d):
+@pytest.mark.parametrize("q", [1, 2])
+def test_coarse_transfer_reproduces_coarse_basis(small2d, q):
     pr, md = small2d
-    P = md.schwarz.P.toarray()
     d = md.disc
+    P = coarse_prolongation(d, pr.elem_coarse, q).toarray()
+    nq0 = (q + 1) * (q + 2) // 2
     ec = pr.elem_coarse
     n0 = ec.max() + 1
     clo = np.array([d.lo[ec == c].min(0) for c in range(n0)])
@@ -114,8 +116,8 @@ def test_coarse_transfer_reproduces_coarse_basis(small2d):
         x = tri[0] + ab[:, :1] * (tri[1] - tri[0]) + ab[:, 1:] * (tri[2] - tri[0])
         phi = eval_basis(x, np.repeat(d.lo[e:e + 1], 4, 0), np.repeat(d.hi[e:e + 1], 4, 0), pr.p)
         c = ec[e]
-        psi = eval_basis(x, np.repeat(clo[c:c + 1], 4, 0), np.repeat(chi[c:c + 1], 4, 0), 1)
-        PK = P[e * pr.nd:(e + 1) * pr.nd, c * 3:(c + 1) * 3]
+        psi = eval_basis(x, np.repeat(clo[c:c + 1], 4, 0), np.repeat(chi[c:c + 1], 4, 0), q)
+        PK = P[e * pr.nd:(e + 1) * pr.nd, c * nq0:(c + 1) * nq0]
         np.testing.assert_allclose(phi @ PK, psi, rtol=0, atol=1e-12 * abs(psi).max())
 
 
