@@ -448,18 +448,107 @@ def bench_table1(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_fig2(args):
+    """Long run of the Table-1 problem (Section 5, Fig. 2 setting): N_h = 4096,
+    p = q = 4, T = 10 ms (4000 steps of 2.5 us), coarse agglomerates H = 4h.
+    Reports iterations over time and, at t = 2, 4.8 and 8.4 ms, the element
+    means of the potential (min, max, depolarised area, an ASCII map).  The
+    ionic constants are not the paper's, so the pictures are qualitative."""
+    import numpy as np
+    import torch
+
+    from paper_2512_19536_amd import _lib, from_problem, initial_state
+    from pdg_inputs import problems
+
+    dev = "cuda:0"
+    n_steps = args.fig2_steps
+    pr = problems.table1_problem(args.fig2_nh, args.fig2_p, args.fig2_h, n_steps=n_steps)
+    log(f"[fig2] {pr.name}: {pr.n_elem} elements, {pr.n_dof} dofs, {int(pr.elem_coarse.max()) + 1} agglomerates")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = from_problem(pr, device=dev, options={_lib.PDG_OPT_GRAPH: 1, _lib.PDG_OPT_CHUNK: 16}, stream=stream)
+    U, Up, Y = initial_state(ctx, pr)
+    n, nd = pr.n_elem, pr.nd
+    # element means: (1, u)_K / |K| with the coefficients c1 of the constant 1
+    _, _, _, mass = ctx.get_matrix()
+    with torch.cuda.stream(stream):
+        c1 = torch.empty(n * nd, dtype=torch.float64, device=dev)
+        ctx.project_p0(torch.ones(1, n, dtype=torch.float64, device=dev), c1)
+    stream.synchronize()
+    M = torch.tensor(mass, device=dev)
+    w = torch.bmm(M, c1.view(n, nd, 1)).view(n, nd)
+    vol = (w * c1.view(n, nd)).sum(1)
+    cen = pr.mesh.element_centroid()
+    gx, gy = 48, 24
+    cell = np.clip((np.floor(cen[:, 0] * gx)).astype(int), 0, gx - 1) + gx * np.clip(
+        (np.floor((1.0 - cen[:, 1]) * gy)).astype(int), 0, gy - 1)
+    snaps_at = {int(round(t / (pr.dt))): t for t in (2.0, 4.8, 8.4)}
+    snaps, iters, t0 = [], [], time.perf_counter()
+    for k in range(1, n_steps + 1):
+        info = ctx.step(U, Up, Y, None, pr.tol, 20000)
+        iters.append(info["iters"])
+        if k in snaps_at:
+            mean = ((w * U.view(n, nd)).sum(1) / vol).cpu().numpy()
+            ascii_rows = []
+            for r in range(gy):
+                row = ""
+                for c in range(gx):
+                    v = mean[cell == r * gx + c]
+                    u = float(v.mean()) if len(v) else float("nan")
+                    row += " " if not np.isfinite(u) else ".:-=+*#%@"[int(np.clip((u + 80.0) / 100.0 * 9, 0, 8))]
+                ascii_rows.append(row)
+            area = float(vol.cpu().numpy()[mean > -40.0].sum())
+            snaps.append({"t_ms": snaps_at[k], "step": k, "u_min": float(mean.min()), "u_max": float(mean.max()),
+                          "depolarised_area_u_gt_-40mV": area, "map": ascii_rows})
+            log(f"[fig2] t = {snaps_at[k]} ms: u in [{mean.min():.1f}, {mean.max():.1f}] mV, area above -40 mV "
+                f"{area:.4f}\n" + "\n".join(ascii_rows))
+        if k % 250 == 0:
+            log(f"[fig2] step {k}: mean iterations of the last 250 steps {np.mean(iters[-250:]):.1f}, "
+                f"{time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if args.fig2_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.fig2_out)), exist_ok=True)
+        with open(args.fig2_out, "w") as f:
+            json.dump({"problem": pr.name, "iters": iters, "snapshots": snaps}, f)
+    out = {
+        "metric": "long run (T = 10 ms) of the Table-1 problem: iterations over time, potential snapshots",
+        "value": round(pr.n_dof * n_steps / dt / 1e6, 3),
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": n_steps,
+        "warmup": 0,
+        "ms_per_step": round(dt * 1e3 / n_steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{pr.name}: {pr.n_dof} dofs, q = p coarse on H = {args.fig2_h}h agglomerates, "
+                               f"relres 1e-9, {n_steps} steps of 2.5 us, graph replay"},
+        "pcg_iters": {"mean": float(np.mean(iters)), "first": iters[0], "last": iters[-1],
+                      "mean_per_1000_steps": [float(np.mean(iters[i:i + 1000])) for i in range(0, n_steps, 1000)]},
+        "snapshots": [{k: v for k, v in sn.items() if k != "map"} for sn in snaps],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "table1"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "table1", "fig2"])
     ap.add_argument("--t1-p", default="1,4", help="table1: degrees p = q")
     ap.add_argument("--t1-nh", default="512,1024,2048,4096", help="table1: fine mesh sizes N_h")
     ap.add_argument("--t1-h", default="2,4,8,16", help="table1: coarse sizes H / h")
     ap.add_argument("--t1-steps", type=int, default=100, help="table1: time steps per preconditioned cell")
     ap.add_argument("--t1-cg-steps", type=int, default=10, help="table1: time steps per unpreconditioned cell")
     ap.add_argument("--t1-out", default=None, help="table1: JSON file for the cells")
+    ap.add_argument("--fig2-steps", type=int, default=4000, help="fig2: time steps (4000 = 10 ms)")
+    ap.add_argument("--fig2-nh", type=int, default=4096, help="fig2: fine mesh size N_h")
+    ap.add_argument("--fig2-p", type=int, default=4, help="fig2: degree p = q")
+    ap.add_argument("--fig2-h", type=int, default=4, help="fig2: coarse size H / h")
+    ap.add_argument("--fig2-out", default=None, help="fig2: JSON file for iterations and snapshots")
     ap.add_argument("--epochs", type=int, default=30, help="cfg5: training epochs")
     ap.add_argument("--batch-steps", type=int, default=4, help="cfg5: time steps per training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="cfg5: peak learning rate")
@@ -490,6 +579,8 @@ def main():
         return bench_learned(args)
     if args.workload == "table1":
         return bench_table1(args)
+    if args.workload == "fig2":
+        return bench_fig2(args)
     if args.graph is None:
         args.graph = 0
 

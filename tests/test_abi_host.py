@@ -48,6 +48,7 @@ CASES = {
     "3d_p2_q2": lambda: replace(problems.small3d(p=2), coarse_q=2),
     "t1_p2": lambda: problems.table1_problem(48, 2, 2),
     "t1_p4": lambda: problems.table1_problem(40, 4, 2),
+    "t1_p4_q2": lambda: replace(problems.table1_problem(40, 4, 2), coarse_q=2),
 }
 
 

@@ -53,7 +53,19 @@ CASES = {
     "t1_p1": lambda: problems.table1_problem(64, 1, 2),
     "t1_p3": lambda: problems.table1_problem(80, 3, 2),
     "t1_p4": lambda: problems.table1_problem(100, 4, 2),
+    # coarse variants: q < p, and a coarse mesh distinct from (and coarser
+    # than) the subdomains
+    "t1_p4_q2": lambda: replace(problems.table1_problem(100, 4, 2), coarse_q=2),
+    "3d_p3_q2_own_coarse": lambda: _own_coarse(problems.small3d(n_grid=8, p=3, n_sub=6), 3, q=2),
 }
+
+
+def _own_coarse(pr, n_coarse, q):
+    """The problem with coarse agglomerates of its own (RCB, not the subdomains)."""
+    from pdg_inputs.partition import rcb
+    ec = rcb(pr.mesh.element_centroid(), n_coarse, seed=77)
+    assert len(np.unique(ec)) == n_coarse and not np.array_equal(ec, pr.elem_sub)
+    return replace(pr, elem_coarse=ec.astype(np.int32), coarse_q=q)
 
 _cache = {}
 
