@@ -104,6 +104,51 @@ __device__ inline int block_bcast(int v) {
 // barrier per group).
 // Matrices larger than the last-level cache stream their values with
 // non-temporal loads (NT), smaller ones stay cacheable across iterations.
+// Entry i of output row `row` for the launch mode, given acc = (K x)_row,i;
+// adds the entry's share of the mode's dot products to part.
+template <int ND>
+__device__ inline void spmv_out(const DevMatrix &A, const SpmvArgs &a, int row, int i, double acc,
+                                double (&part)[2]) {
+    const int64_t idx = (int64_t)row * ND + i;
+    switch (a.mode) {
+    case SPMV_PLAIN:
+        a.y[idx] = acc;
+        break;
+    case SPMV_PQ:
+        a.y[idx] = acc;
+        part[0] = fma(a.x[idx], acc, part[0]);
+        break;
+    case SPMV_RESID: {
+        const double bv = a.b[idx], rv = bv - acc;
+        a.y[idx] = rv;
+        if (a.xcopy) a.xcopy[idx] = a.x[idx];
+        if (a.u_prev) a.u_prev[idx] = a.x[idx];
+        part[0] = fma(bv, bv, part[0]);
+        part[1] = fma(rv, rv, part[1]);
+        break;
+    }
+    case SPMV_STEP:
+    case SPMV_RHS: {
+        const double *Mr = A.mass + (int64_t)row * ND * ND;
+        const double *ur = a.x + (int64_t)row * ND;
+        double mu = 0.0;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) mu = fma(Mr[j * ND + i], ur[j], mu);
+        double bv = a.two_c * mu - acc - a.chi * a.I[idx];
+        if (a.f) bv += a.f[idx];
+        if (a.mode == SPMV_RHS) {
+            a.y[idx] = bv;
+        } else {
+            a.y[idx] = bv - acc;  // r0 = b - K u  (x0 = u)
+            a.u_prev[idx] = ur[i];
+            if (a.xcopy) a.xcopy[idx] = ur[i];
+            part[0] = fma(bv, bv, part[0]);
+        }
+        break;
+    }
+    }
+}
+
 template <int ND, int WPG, bool NT>
 __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
@@ -166,44 +211,66 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
         if (w != 0) continue;  // wave 0 finishes the group
         const int row = (r < G) ? A.grp_rows[g * G + r] : -1;
         if (row < 0) continue;
-        const int64_t idx = (int64_t)row * ND + i;
-        switch (a.mode) {
-        case SPMV_PLAIN:
-            a.y[idx] = acc;
-            break;
-        case SPMV_PQ:
-            a.y[idx] = acc;
-            part[0] = fma(a.x[idx], acc, part[0]);
-            break;
-        case SPMV_RESID: {
-            const double bv = a.b[idx], rv = bv - acc;
-            a.y[idx] = rv;
-            if (a.xcopy) a.xcopy[idx] = a.x[idx];
-            if (a.u_prev) a.u_prev[idx] = a.x[idx];
-            part[0] = fma(bv, bv, part[0]);
-            part[1] = fma(rv, rv, part[1]);
-            break;
-        }
-        case SPMV_STEP:
-        case SPMV_RHS: {
-            const double *Mr = A.mass + (int64_t)row * ND * ND;
-            const double *ur = a.x + (int64_t)row * ND;
-            double mu = 0.0;
+        spmv_out<ND>(A, a, row, i, acc, part);
+    }
+    if (w != 0 || a.mode == SPMV_PLAIN || a.mode == SPMV_RHS) return;
+    wave_sum<2>(part);
+    if (lane == 0) {
+        a.part[2 * blockIdx.x] = part[0];
+        a.part[2 * blockIdx.x + 1] = part[1];
+    }
+}
+
+// Blocks of more than 32 rows (3-D, p = 4: nd = 35) give one element row per
+// group, and the mapping above would leave 29 of 64 lanes idle.  Here the
+// (slot, row) pairs of the group's blocks are laid end to end and each lane
+// takes one pair per step: for every trial index j a wavefront's load then
+// covers 64 consecutive pairs (at most two contiguous runs of the slot-major
+// layout).  Each pair's dot product goes to LDS, and lane i of wave 0 adds
+// row i's products in slot order, so the result does not depend on WPG.
+template <int ND, int WPG, bool NT>
+__global__ __launch_bounds__(64 * WPG) void k_spmv_wide(DevMatrix A, SpmvArgs a) {
+    constexpr int CH = 16;  // slots per LDS chunk
+    constexpr int T = CH * ND;
+    constexpr int STEPS = (T + 63) / 64;
+    __shared__ double s_p[T];
+    const int64_t g_begin = A.wg_g0[blockIdx.x], g_end = A.wg_g0[blockIdx.x + 1];
+    if (a.mode == SPMV_PQ && a.sc[A.grp_sys[g_begin]].done) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double part[2] = {0.0, 0.0};
+    for (int64_t g = g_begin; g < g_end; ++g) {
+        const int64_t s0 = A.grp_slot_off[g], ns = A.grp_slot_off[g + 1] - s0;
+        const int32_t *colp = A.grp_col + s0;
+        const double *vp = A.grp_val + s0 * ND * ND;
+        double acc = 0.0;
+        for (int64_t c0 = 0; c0 < ns; c0 += CH) {
+            const int nch = (int)(ns - c0 < CH ? ns - c0 : CH);
+            const int tn = nch * ND;
+            for (int k = w; k < STEPS; k += WPG) {
+                const int t = k * 64 + lane;
+                if (t >= tn) continue;
+                const int sl = t / ND, i = t - sl * ND;
+                const int col = colp[c0 + sl];
+                double sum = 0.0;
+                if (col >= 0) {
+                    const double *vs = vp + (c0 + sl) * ND * ND + i;
+                    const double *xb = a.x + (int64_t)col * ND;
+                    double v[ND];
 #pragma unroll
-            for (int j = 0; j < ND; ++j) mu = fma(Mr[j * ND + i], ur[j], mu);
-            double bv = a.two_c * mu - acc - a.chi * a.I[idx];
-            if (a.f) bv += a.f[idx];
-            if (a.mode == SPMV_RHS) {
-                a.y[idx] = bv;
-            } else {
-                a.y[idx] = bv - acc;  // r0 = b - K u  (x0 = u)
-                a.u_prev[idx] = ur[i];
-                if (a.xcopy) a.xcopy[idx] = ur[i];
-                part[0] = fma(bv, bv, part[0]);
+                    for (int j = 0; j < ND; ++j) v[j] = NT ? __builtin_nontemporal_load(vs + j * ND) : vs[j * ND];
+#pragma unroll
+                    for (int j = 0; j < ND; ++j) sum = fma(v[j], xb[j], sum);
+                }
+                s_p[t] = sum;
             }
-            break;
+            __syncthreads();
+            if (w == 0 && lane < ND)
+                for (int sl = 0; sl < nch; ++sl) acc += s_p[sl * ND + lane];
+            __syncthreads();
         }
-        }
+        if (w != 0 || lane >= ND) continue;
+        const int row = A.grp_rows[g];
+        if (row >= 0) spmv_out<ND>(A, a, row, lane, acc, part);
     }
     if (w != 0 || a.mode == SPMV_PLAIN || a.mode == SPMV_RHS) return;
     wave_sum<2>(part);
@@ -1116,10 +1183,17 @@ __global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
 // launchers
 template <int ND, int WPG>
 static hipError_t spmv_nd_w(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    if (A.nt)
-        hipLaunchKernelGGL((k_spmv<ND, WPG, true>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
-    else
-        hipLaunchKernelGGL((k_spmv<ND, WPG, false>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+    if constexpr (ND > 32) {
+        if (A.nt)
+            hipLaunchKernelGGL((k_spmv_wide<ND, WPG, true>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+        else
+            hipLaunchKernelGGL((k_spmv_wide<ND, WPG, false>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+    } else {
+        if (A.nt)
+            hipLaunchKernelGGL((k_spmv<ND, WPG, true>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+        else
+            hipLaunchKernelGGL((k_spmv<ND, WPG, false>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
+    }
     return hipGetLastError();
 }
 
