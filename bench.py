@@ -253,8 +253,10 @@ def bench_learned(args):
     macs = learned.N_IN * W + 2 * W * W + W * learned.N_OUT
     flops = rows * 2 * (2 * macs + (2 * W * W + W * learned.N_OUT))
     tflops = flops / (ms_train_step * 1e-3) / 1e12
+    step_bytes = mlp_train_step_bytes(rows)
+    mlp_gbs = step_bytes / (ms_train_step * 1e-3) / 1e9
     log(f"[bench] training: {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}; train step {ms_train_step:.3f} ms "
-        f"({rows} rows, {tflops:.1f} TFLOP/s BF16)")
+        f"({rows} rows, {tflops:.1f} TFLOP/s BF16, {step_bytes / 1e6:.0f} MB moved -> {mlp_gbs:.0f} GB/s)")
     recs = [learned.evaluate(net, q, args.traj_steps, log=log) for q in test_p]
     n_l = sum(r["schwarz_timing"][0] for r in recs)
     t_l = sum(r["schwarz_timing"][1] for r in recs)
@@ -308,16 +310,50 @@ def bench_learned(args):
             "avg_launch_us": round(t_l / max(n_l, 1) * 1e3, 2),
         },
         "mlp_training_roofline": {
-            "kernel": "k_gemm_nt (BF16 MFMA layer products) in one training step",
-            "bound": "mfma",
-            "achieved": round(tflops, 2),
-            "peak": 2500.0,
-            "unit": "TFLOP/s",
-            "frac": round(tflops / 2500.0, 5),
+            "kernel": "one training step (BF16 MFMA layer products, loss, bias gradients, split sums, Adam)",
+            "bound": "hbm",
+            "achieved": round(mlp_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(mlp_gbs / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_step": int(step_bytes),
+            "mfma_tflops": round(tflops, 2),
+            "mfma_frac_of_2.5_pflops": round(tflops / 2500.0, 5),
+            "arithmetic_intensity_flop_per_byte": round(flops / step_bytes, 1),
         },
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
+
+
+def mlp_train_step_bytes(rows, split_rows=1024):
+    """Algorithmic HBM bytes of one training step of the 96-256-256-256-32 MLP
+    on `rows` samples: every product reads its operands once and writes its
+    outputs (bf16 activations and gradients with their transposed copies,
+    fp32 last-layer output and split partials), plus the loss, bias-gradient,
+    split-sum and Adam passes.  At 52 flop/byte the step sits far below the
+    BF16 ridge point (2.5 PFLOP/s / 8 TB/s = 312 flop/byte): HBM bounds it."""
+    from paper_2512_19536_amd import learned
+    dims = [learned.N_IN, learned.WIDTH, learned.WIDTH, learned.WIDTH, learned.N_OUT]
+    bf, f4 = 2, 4
+    splits = -(-rows // split_rows)
+    b = 0
+    for l in range(4):
+        K, N = dims[l], dims[l + 1]
+        b += rows * K * bf + N * K * bf                                  # forward operands
+        b += rows * N * (2 * bf if l < 3 else f4)                        # H and H^T, or Y
+    n_out = dims[-1]
+    b += rows * n_out * (2 * f4 + 2 * bf) + rows * 4                     # loss: Y, T -> dY, dY^T; row weights
+    for l in range(3, -1, -1):
+        K, N = dims[l], dims[l + 1]
+        b += N * rows * bf + K * rows * bf + splits * N * K * f4         # weight gradient: dY^T, H^T -> partials
+        b += splits * N * K * f4 + N * K * f4                            # split sums
+        b += N * rows * bf + N * f4                                      # bias gradient
+        if l > 0:
+            b += rows * N * bf + K * N * bf + rows * K * bf + rows * K * 2 * bf  # data gradient with ReLU mask
+    n_par = sum(dims[l] * dims[l + 1] + dims[l + 1] for l in range(4))
+    b += n_par * (4 * f4 + 3 * f4) + 2 * n_par * bf                      # Adam: theta, m, v, grad -> theta, m, v; bf16 copies
+    return b
 
 
 def _mesh_h(mesh):

@@ -34,7 +34,8 @@ __device__ inline uint16_t f2bf(float f) {
 
 __device__ inline bf16x8 load8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const uint4 *)p); }
 
-// One wavefront per 32 x 32 output tile (2 x 2 MFMA tiles of 16 x 16).
+// Narrow products (32 output columns): one wavefront per 32 x 32 output tile
+// (2 x 2 MFMA tiles of 16 x 16), operands straight from global memory.
 // Operand layout of v_mfma_f32_16x16x32_bf16: lane l supplies row l % 16 of
 // the A tile and column l % 16 of the B tile at reduction indices
 // 8 (l / 16) .. 8 (l / 16) + 7, i.e. one 16-byte load from each operand's row;
@@ -97,6 +98,128 @@ __global__ __launch_bounds__(64) void k_gemm_nt(GemmArgs a) {
         }
 }
 
+// Products with at least 64 output columns: a workgroup of nw wavefronts
+// computes a 64 x 32nw tile, each wavefront 64 x 32 (4 x 2 MFMA tiles).  The
+// A rows of the tile are staged in LDS per reduction chunk of 256 with
+// 16-byte loads (read once instead of once per 32 columns); the wavefront's
+// B fragments for the chunk are requested first, so they arrive while A is
+// staged.  The epilogue (bias, ReLU) runs in registers, then the tile goes
+// through LDS as bf16 so that C, the ReLU mask and CT move in 16-byte pieces.
+// Every accumulator receives the same MFMA sequence (k ascending) as in the
+// one-wavefront kernel below, so both give the same bits.
+constexpr int kGemmKc = 256, kGemmLdsRow = kGemmKc + 8;
+
+__global__ __launch_bounds__(512) void k_gemm_nt_wide(GemmArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_t[64 * kGemmLdsRow];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * 64;
+    const int nb = 32 * nw, nb0 = blockIdx.y * nb, n0 = nb0 + 32 * w;
+    const int64_t kz0 = (int64_t)blockIdx.z * a.k_chunk;
+    const int64_t kz1 = kz0 + a.k_chunk < a.K ? kz0 + a.k_chunk : a.K;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t kc0 = kz0; kc0 < kz1; kc0 += kGemmKc) {
+        const int kc = (int)(kz1 - kc0 < kGemmKc ? kz1 - kc0 : kGemmKc);
+        const int nst = kc >> 5, npr = kc >> 3;
+        bf16x8 fb[kGemmKc / 32][2];
+        const uint16_t *pb = a.B + (int64_t)(n0 + r) * a.ldb + kc0 + kq;
+#pragma unroll
+        for (int st = 0; st < kGemmKc / 32; ++st)
+            if (st < nst) {
+                fb[st][0] = load8(pb + 32 * st);
+                fb[st][1] = load8(pb + 16 * a.ldb + 32 * st);
+            }
+        for (int t = tid; t < 64 * npr; t += blockDim.x) {
+            const int row = t / npr, q = t - row * npr;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (m0 + row < a.M) v = *(const uint4 *)(a.A + (m0 + row) * a.lda + kc0 + 8 * q);
+            *(uint4 *)(s_t + row * kGemmLdsRow + 8 * q) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < kGemmKc / 32; ++st) {
+            if (st >= nst) break;
+            bf16x8 fa[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = *(const bf16x8 *)(s_t + (16 * i + r) * kGemmLdsRow + 32 * st + kq);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[st][j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int rq = (lane >> 4) * 4, c = lane & 15;
+    if (a.P) {
+        float *P = a.P + (int64_t)blockIdx.z * a.M * a.N;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = m0 + 16 * i + rq + v;
+                    if (row < a.M) P[row * a.N + n0 + 16 * j + c] = acc[i][j][v];
+                }
+        return;
+    }
+    const int ldp = nb + 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = 16 * i + rq + v, cl = 32 * w + 16 * j + c;
+                const int64_t row = m0 + rl;
+                const int col = nb0 + cl;
+                float x = acc[i][j][v];
+                if (a.bias) x += a.bias[col];
+                if (a.relu) x = x > 0.f ? x : 0.f;
+                if (a.Cf && row < a.M) {
+                    // (no product here asks for both; kept exact for any caller)
+                    const float xm = a.mask && !(bf2f(a.mask[row * a.ldm + col]) > 0.f) ? 0.f : x;
+                    a.Cf[row * a.ldcf + col] = xm;
+                }
+                s_t[rl * ldp + cl] = f2bf(x);
+            }
+    __syncthreads();
+    // row-major pass: the mask (a zero keeps the bits of f2bf(0)) and C
+    if (a.mask || a.C)
+        for (int t = tid; t < 64 * (nb >> 3); t += blockDim.x) {
+            const int rl = t / (nb >> 3), q = t - rl * (nb >> 3);
+            const int64_t row = m0 + rl;
+            if (row >= a.M) continue;
+            uint16_t *sp = s_t + rl * ldp + 8 * q;
+            if (a.mask) {
+                uint16_t mk[8], hv[8];
+                *(uint4 *)mk = *(const uint4 *)(a.mask + row * a.ldm + nb0 + 8 * q);
+                *(uint4 *)hv = *(const uint4 *)sp;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (!(bf2f(mk[e]) > 0.f)) hv[e] = 0;
+                *(uint4 *)sp = *(const uint4 *)hv;
+            }
+            if (a.C) *(uint4 *)(a.C + row * a.ldc + nb0 + 8 * q) = *(const uint4 *)sp;
+        }
+    if (a.CT) {
+        __syncthreads();
+        for (int t = tid; t < nb * 8; t += blockDim.x) {
+            const int cl = t >> 3, q = t & 7;
+            if (m0 + 8 * q >= a.M) continue;
+            uint16_t hv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) hv[e] = s_t[(8 * q + e) * ldp + cl];
+            *(uint4 *)(a.CT + (int64_t)(nb0 + cl) * a.ldct + m0 + 8 * q) = *(const uint4 *)hv;
+        }
+    }
+}
+
 __global__ void k_reduce_splits(const float *P, int splits, int64_t n, float *out) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.f;
@@ -105,12 +228,18 @@ __global__ void k_reduce_splits(const float *P, int splits, int64_t n, float *ou
     }
 }
 
-// One block per output feature: fixed-order sum over the samples.
+// One block per output feature: fixed-order sum over the samples, eight
+// per 16-byte load (rows and ld are multiples of 32).
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *dYT, int64_t rows, int64_t ld, float *db) {
     __shared__ float sh[256];
     const int n = blockIdx.x;
     float s = 0.f;
-    for (int64_t m = threadIdx.x; m < rows; m += 256) s += bf2f(dYT[n * ld + m]);
+    for (int64_t m = 8 * (int64_t)threadIdx.x; m < rows; m += 8 * 256) {
+        uint16_t h[8];
+        *(uint4 *)h = *(const uint4 *)(dYT + n * ld + m);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += bf2f(h[e]);
+    }
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -263,8 +392,19 @@ static int grid_for(int64_t n) {
 hipError_t launch_gemm(const GemmArgs &a, int splits, hipStream_t s) {
     if (a.M % 32 || a.N % 32 || a.K % 32 || a.k_chunk % 32 || splits < 1) return hipErrorInvalidValue;
     if ((int64_t)splits * a.k_chunk < a.K) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm_nt, dim3((unsigned)(a.M / 32), (unsigned)(a.N / 32), (unsigned)splits), dim3(64), 0, s,
-                       a);
+    if (a.lda % 8 || a.ldb % 8) return hipErrorInvalidValue;  // 16-byte operand loads
+    const bool ld16 = !(a.C && a.ldc % 8) && !(a.mask && a.ldm % 8) && !(a.CT && a.ldct % 8);
+    if (a.N >= 64 && ld16) {
+        // widest tile of at most 8 wavefronts that divides N
+        int nw = 8;
+        while ((a.N / 32) % nw) --nw;
+        hipLaunchKernelGGL(k_gemm_nt_wide, dim3((unsigned)((a.M + 63) / 64), (unsigned)(a.N / (32 * nw)),
+                                                (unsigned)splits),
+                           dim3(64 * nw), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_gemm_nt, dim3((unsigned)(a.M / 32), (unsigned)(a.N / 32), (unsigned)splits), dim3(64), 0,
+                           s, a);
+    }
     return hipGetLastError();
 }
 
@@ -274,6 +414,7 @@ hipError_t launch_reduce_splits(const float *P, int splits, int64_t n, float *ou
 }
 
 hipError_t launch_bias_grad(const uint16_t *dYT, int n_out, int64_t rows, int64_t ld, float *db, hipStream_t s) {
+    if (rows % 8 || ld % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bias_grad, dim3(n_out), dim3(256), 0, s, dYT, rows, ld, db);
     return hipGetLastError();
 }
