@@ -163,6 +163,32 @@ def bench_batch(args):
         log(f"[bench] p={bs.problems[ci].p}: schwarz apply {n} launches, avg {ms / max(n, 1) * 1e3:.1f} us, "
             f"{by / 1e6:.1f} MB -> {by / (ms / max(n, 1) * 1e-3) / 1e9 if n else 0:.0f} GB/s")
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    # the SpMV moves the most bytes in this workload (the p = 3, 4 matrices):
+    # each context's SpMV on its own, HIP events on the context's stream
+    sp_ms, sp_bytes, sp_launches, sp_ctx = 0.0, 0.0, 0, []
+    for ci, c in enumerate(bs.ctxs):
+        _, nd_c, n_dof_c, nnzb = c.get_sizes()
+        by = nnzb * nd_c * nd_c * 8 + 2 * n_dof_c * 8
+        x = U[ci]
+        y = torch.empty_like(x)
+        reps = 10
+        with torch.cuda.stream(c.stream):
+            c.spmv(x, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(c.stream)
+            for _ in range(reps):
+                c.spmv(x, y)
+            e1.record(c.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        sp_ms += ms
+        sp_bytes += reps * by
+        sp_launches += reps
+        sp_ctx.append({"p": bs.problems[ci].p, "avg_us": round(ms / reps * 1e3, 1), "bytes": int(by),
+                       "gb_s": round(by / (ms / reps * 1e-3) / 1e9, 1)})
+        log(f"[bench] p={bs.problems[ci].p}: spmv {ms / reps * 1e3:.1f} us, {by / 1e6:.1f} MB -> "
+            f"{by / (ms / reps * 1e-3) / 1e9:.0f} GB/s")
+    sp_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9 if sp_ms > 0 else 0.0
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle ...")
@@ -192,6 +218,18 @@ def bench_batch(args):
                                                                                  "max": max(sys_iters)}},
         "autotune": tune,
         "roofline": {
+            "kernel": "k_spmv (element-block SpMV), each degree context on its own",
+            "bound": "hbm",
+            "achieved": round(sp_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(sp_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes_per_launch": int(sp_bytes / max(sp_launches, 1)),
+            "avg_launch_us": round(sp_ms / max(sp_launches, 1) * 1e3, 2),
+            "per_context": sp_ctx,
+        },
+        "schwarz_roofline": {
             "kernel": "k_schwarz (local + coarse inverse-tile products), all degree contexts",
             "bound": "hbm",
             "achieved": round(achieved, 1),

@@ -197,7 +197,7 @@ typedef enum {
     PDG_OPT_CHUNK = 2,          /* PCG iterations launched between host convergence polls (>= 1) */
     PDG_OPT_KERNEL_TIMING = 3,  /* 1: time every Schwarz-apply launch with HIP events */
     PDG_OPT_SCHWARZ_ITEM_KB = 4,/* target tile bytes (KiB) per Schwarz work item, 32..8192,
-                                   default 256; set before pdg_setup_preconditioner */
+                                   default 192; set before pdg_setup_preconditioner */
     PDG_OPT_GRAPH = 5,          /* 1: replay each chunk of PCG iterations as a captured HIP graph
                                    (captured on first use; not while kernel timing is on);
                                    needs a non-NULL stream in pdg_create (else PDG_EINVAL) */
@@ -218,12 +218,14 @@ pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 pdg_status pdg_kernel_timing(pdg_ctx *ctx, int64_t *launches, double *total_ms,
                              double *bytes_per_launch);
 
-/* Autotuner: times the Schwarz apply for work items of 64, 128, 256, 512 and
- * 1024 KiB of tiles (those whose items fit in 64 KiB of LDS) and the SpMV
- * with 1, 2, 4 and 8 wavefronts per block-row group, `reps` launches each
- * (1..1000), with HIP events on the context's stream, and keeps the fastest
- * of each.  Results do not change (only the work split and the summation
- * order of the Schwarz partials do).  Synchronises.  Call after
+/* Autotuner: times the Schwarz apply for work items of 64, 96, 128, 192, 256,
+ * 384, 512 and 1024 KiB of tiles (those whose items fit in 64 KiB of LDS) and
+ * the SpMV with 1, 2, 4 and 8 wavefronts per block-row group, `reps` launches
+ * each (1..1000), with HIP events on the context's stream, and keeps the
+ * fastest of each.  The choice changes results only at rounding level: it
+ * sets the work split, and with it the order in which Schwarz partials (and,
+ * for blocks of up to 32 rows, SpMV wavefront partials) are added; runs with
+ * the same choice stay bitwise equal.  Synchronises.  Call after
  * pdg_bind_workspace. */
 typedef struct {
     int32_t item_kb;      /* chosen Schwarz work-item size (KiB) */

@@ -81,7 +81,7 @@ struct pdg_ctx {
     std::string err;
     int n_threads = 0;
     // options
-    int true_resid = 0, chunk = 4, timing = 0, item_kb = 256, use_graph = 0, spmv_wpg = 4;
+    int true_resid = 0, chunk = 4, timing = 0, item_kb = 192, use_graph = 0, spmv_wpg = 4;
     int prev_iters = 0;
     // host data
     Mesh mesh;
@@ -1571,7 +1571,7 @@ pdg_status pdg_autotune(pdg_ctx *c, int32_t reps, pdg_tune_result *out) {
             double *r = vec(c, c->w.r);
             HIPCHK(launch_status_reset(sc, c->n_sys, -1.0, 0, 0, s));
             HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.t), r, sc), s));
-            const int cand[] = {64, 128, 256, 512, 1024};
+            const int cand[] = {64, 96, 128, 192, 256, 384, 512, 1024};
             int best_kb = c->item_kb;
             double best = 1e300;
             for (int kb : cand) {
