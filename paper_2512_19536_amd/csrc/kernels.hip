@@ -92,18 +92,6 @@ __device__ inline int block_bcast(int v) {
     return r;
 }
 
-// ---------------------------------------------------------------------------
-// Block-sparse SpMV over element rows in interleaved group-ELL form.
-// G = 64 / ND element rows form a group; lane (r, i) = (lane / ND, lane % ND)
-// owns output row i of the group's r-th element.  Group values are stored
-// slot-major so that for every (slot s, trial index j) a wavefront reads G*ND
-// consecutive doubles:  val[((s * ND + j) * G + r) * ND + i] = K_{row_r, col_{s,r}}[i][j].
-// A workgroup owns a contiguous run of groups (of one system) and writes one
-// partial sum; its WPG wavefronts take each group's slots round-robin and
-// their sums are added in wave order through LDS (double-buffered, one
-// barrier per group).
-// Matrices larger than the last-level cache stream their values with
-// non-temporal loads (NT), smaller ones stay cacheable across iterations.
 // Entry i of output row `row` for the launch mode, given acc = (K x)_row,i;
 // adds the entry's share of the mode's dot products to part.
 template <int ND>
@@ -149,6 +137,18 @@ __device__ inline void spmv_out(const DevMatrix &A, const SpmvArgs &a, int row, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Block-sparse SpMV over element rows in interleaved group-ELL form.
+// G = 64 / ND element rows form a group; lane (r, i) = (lane / ND, lane % ND)
+// owns output row i of the group's r-th element.  Group values are stored
+// slot-major so that for every (slot s, trial index j) a wavefront reads G*ND
+// consecutive doubles:  val[((s * ND + j) * G + r) * ND + i] = K_{row_r, col_{s,r}}[i][j].
+// A workgroup owns a contiguous run of groups (of one system) and writes one
+// partial sum; its WPG wavefronts take each group's slots round-robin and
+// their sums are added in wave order through LDS (double-buffered, one
+// barrier per group).
+// Matrices larger than the last-level cache stream their values with
+// non-temporal loads (NT), smaller ones stay cacheable across iterations.
 template <int ND, int WPG, bool NT>
 __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
@@ -649,6 +649,66 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const int64_t i1 = (i0 + 256 < n ? i0 + 256 : n) - 1;
     const int64_t idx = i0 + threadIdx.x;
     const int my = idx < n ? a.elem_sys[idx / nd] : -1;
+    // z = B r depends only on the Schwarz partials, not on this launch's
+    // reductions, so it is formed first (for every dof of the block, also of
+    // systems that turn out to be done; those values are dropped) and its
+    // memory latency does not add to that of the reductions below.
+    const double p_old = (my >= 0 && a.mode == 2) ? a.p[idx] : 0.0;
+    // coarse values z0 of the block's coarse elements, once per block: the
+    // block's elements usually lie in one or two coarse elements (numbered
+    // contiguously), so the block computes their KMAX * NQ values into LDS
+    constexpr int KMAX = 8;
+    __shared__ double s_z0[KMAX * (NQ > 0 ? NQ : 1)];
+    __shared__ int s_cr[2];
+    int c_lo = 0, n_c = KMAX + 1;
+    if (NQ > 0) {
+        if (threadIdx.x == 0) {
+            s_cr[0] = a.elem_coarse[i0 / nd];
+            s_cr[1] = a.elem_coarse[i1 / nd];
+        }
+        __syncthreads();
+        c_lo = s_cr[0];
+        n_c = s_cr[1] - c_lo + 1;
+        // the range holds every element's coarse element only if it is monotone over the block
+        const int ce = idx < n ? a.elem_coarse[idx / nd] : c_lo;
+        const int bad = __syncthreads_or(ce < c_lo || ce >= c_lo + n_c);
+        if (bad || n_c > KMAX || n_c < 1) n_c = KMAX + 1;
+        if (n_c <= KMAX) {
+            for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
+                const int c = c_lo + t / NQ, j = t % NQ;
+                const int b = a.coarse_sys[c];
+                const int gi = (c - a.csys_ce0[b]) * NQ + j;
+                s_z0[t] = tile_row_value(a, a.coarse_rt0[b] + (gi >> 6), gi & 63);
+            }
+            __syncthreads();
+        }
+    }
+    double zz = 0.0;
+    if (my >= 0) {
+        if (a.r_ident) {
+            zz = a.r_ident[idx];
+        } else {
+            const int dr = a.dof_rt[idx];
+            zz = tile_row_value(a, dr >> 6, dr & 63);
+        }
+        if (NQ > 0) {
+            const int64_t e = idx / nd;
+            const int ce = a.elem_coarse[e];
+            const double *Pr = a.P + idx * NQ;
+            if (n_c <= KMAX) {
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
+            } else {
+                const int g0 = (ce - a.csys_ce0[my]) * NQ;
+                const int rt0 = a.coarse_rt0[my];
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) {
+                    const int gi = g0 + j;
+                    zz = fma(Pr[j], tile_row_value(a, rt0 + (gi >> 6), gi & 63), zz);
+                }
+            }
+        }
+    }
     double beta = 0.0;
     bool active = a.mode == 0 && my >= 0;
     if (a.mode != 0) {
@@ -705,61 +765,8 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
             }
         }
     }
-    // coarse values z0 of the block's coarse elements, once per block: the
-    // block's elements usually lie in one or two coarse elements (numbered
-    // contiguously), so the block computes their KMAX * NQ values into LDS
-    constexpr int KMAX = 8;
-    __shared__ double s_z0[KMAX * (NQ > 0 ? NQ : 1)];
-    __shared__ int s_cr[2];
-    int c_lo = 0, n_c = KMAX + 1;
-    if (NQ > 0) {
-        if (threadIdx.x == 0) {
-            s_cr[0] = a.elem_coarse[i0 / nd];
-            s_cr[1] = a.elem_coarse[i1 / nd];
-        }
-        __syncthreads();
-        c_lo = s_cr[0];
-        n_c = s_cr[1] - c_lo + 1;
-        // the range holds every element's coarse element only if it is monotone over the block
-        const int ce = idx < n ? a.elem_coarse[idx / nd] : c_lo;
-        const int bad = __syncthreads_or(ce < c_lo || ce >= c_lo + n_c);
-        if (bad || n_c > KMAX || n_c < 1) n_c = KMAX + 1;
-        if (n_c <= KMAX) {
-            for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
-                const int c = c_lo + t / NQ, j = t % NQ;
-                const int b = a.coarse_sys[c];
-                const int gi = (c - a.csys_ce0[b]) * NQ + j;
-                s_z0[t] = tile_row_value(a, a.coarse_rt0[b] + (gi >> 6), gi & 63);
-            }
-            __syncthreads();
-        }
-    }
     if (!active) return;
-    double zz;
-    if (a.r_ident) {
-        zz = a.r_ident[idx];
-    } else {
-        const int dr = a.dof_rt[idx];
-        zz = tile_row_value(a, dr >> 6, dr & 63);
-    }
-    if (NQ > 0) {
-        const int64_t e = idx / nd;
-        const int ce = a.elem_coarse[e];
-        const double *Pr = a.P + idx * NQ;
-        if (n_c <= KMAX) {
-#pragma unroll
-            for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
-        } else {
-            const int g0 = (ce - a.csys_ce0[my]) * NQ;
-            const int rt0 = a.coarse_rt0[my];
-#pragma unroll
-            for (int j = 0; j < NQ; ++j) {
-                const int gi = g0 + j;
-                zz = fma(Pr[j], tile_row_value(a, rt0 + (gi >> 6), gi & 63), zz);
-            }
-        }
-    }
-    if (a.mode == 2) zz = fma(beta, a.p[idx], zz);
+    if (a.mode == 2) zz = fma(beta, p_old, zz);
     a.p[idx] = zz;
 }
 
