@@ -205,10 +205,14 @@ typedef enum {
     PDG_OPT_PRECONDITIONER = 7, /* 1 (default): two-level additive Schwarz B_ad^{-1} of eq. (5);
                                    0: none (B = I, plain CG), the reference rows of the paper's
                                    Table 1.  pdg_precond_apply then copies r to z. */
-    PDG_OPT_LANCZOS_CAP = 8     /* PCG coefficients (alpha_j, beta_j) kept per system for
+    PDG_OPT_LANCZOS_CAP = 8,    /* PCG coefficients (alpha_j, beta_j) kept per system for
                                    pdg_lanczos, 1..2^20 (default 2048; 16 bytes each per
                                    system in the workspace).  Set before pdg_workspace_query /
                                    pdg_bind_workspace. */
+    PDG_OPT_ION_EXTRAPOLATION = 9 /* the potential in the explicit ion term of eq. (4):
+                                   0 (default): u~ = (3 u^k - u^(k-1)) / 2, extrapolated to the
+                                   Crank-Nicolson mid-point t^(k+1/2);
+                                   1: u~ = 2 u^k - u^(k-1), extrapolated to t^(k+1) */
 } pdg_option;
 pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 
@@ -251,7 +255,8 @@ pdg_status pdg_precond_apply(pdg_ctx *ctx, const double *r, double *z);
 
 /* Ionic update (second line of eq. (4)) and ion term: ions [5][n_elem][nd]
  * Y^k -> Y^(k+1) in place; I[e][i] = int_K f(u~, y^(k+1)) phi_i with the
- * extrapolated potential u~ = (3 u^k - u^(k-1)) / 2.
+ * extrapolated potential u~ = (3 u^k - u^(k-1)) / 2 (or 2 u^k - u^(k-1), see
+ * PDG_OPT_ION_EXTRAPOLATION).
  * Returns PDG_ENONFINITE (synchronising) if a concentration was <= 0. */
 pdg_status pdg_ionic(pdg_ctx *ctx, const double *u, const double *u_prev, double *ions,
                      double *I);

@@ -10,7 +10,8 @@ Per step k (Section 3):
    mid-point, u~ = (3 u_h^k - u_h^(k-1)) / 2 (reading of the paper's
    "second-order explicit extrapolation": the Adams-Bashforth-2 partner of the
    Crank-Nicolson mid-point rule; the extrapolation to t^(k+1),
-   2 u^k - u^(k-1), is unstable at dt = 0.05 ms with this ionic model);
+   2 u^k - u^(k-1), is unstable at dt = 0.05 ms with this ionic model; it is
+   available as ``problem.ion_extrap = "endpoint"``);
    at k = 0, U^(-1) := U^(0);
 3. right-hand side of the first line of eq. (4) divided by dt:
    b = (c M - 1/2 A) U^k - chi_m I + F = 2 c M U^k - K U^k - chi_m I + F,
@@ -39,6 +40,9 @@ class Monodomain:
         self.Mmat = d.mass_matrix()
         self.Minv = np.linalg.inv(d.M)
         self.prm = np.asarray(problem.ionic, dtype=np.float64)
+        # u~ of the ion term: (3u^k - u^(k-1))/2 at the mid-point, or 2u^k - u^(k-1) at t^(k+1)
+        mode = getattr(problem, "ion_extrap", "midpoint")
+        self.ext = {"midpoint": (1.5, -0.5), "endpoint": (2.0, -1.0)}[mode]
         self.schwarz = None
         if with_schwarz:
             self.schwarz = Schwarz(d, self.K, problem.elem_sub, problem.elem_coarse, problem.coarse_q)
@@ -79,7 +83,7 @@ class Monodomain:
             for l in range(Ye.shape[0]):
                 np.add.at(G[l], el - e0, (w * mq[l])[:, None] * phi)
             Ynew[:, e0:e1] = Ye[:, e0:e1] - dt * np.einsum("eij,lej->lei", self.Minv[e0:e1], G)
-            ut = 1.5 * uq - 0.5 * np.einsum("qi,qi->q", phi, Upe[el])
+            ut = self.ext[0] * uq + self.ext[1] * np.einsum("qi,qi->q", phi, Upe[el])
             yn = np.einsum("qi,lqi->lq", phi, Ynew[:, el])
             fq = ionic.f_ion(ut, yn, self.prm)
             np.add.at(I, el, (w * fq)[:, None] * phi)

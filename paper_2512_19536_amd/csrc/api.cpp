@@ -111,6 +111,7 @@ struct pdg_ctx {
     int pre_rr = 0;              // same for (r, r) when no preconditioner is applied
     bool no_precond = false;     // B = I: plain CG
     int lcap = 2048;             // PCG coefficients kept per system (Lanczos estimate)
+    int ion_endpoint = 0;        // ion term at 2u^k - u^(k-1) instead of (3u^k - u^(k-1))/2
     bool lanczos_ok = false;     // device scalars still hold the last solve
     // group-ELL matrix (host staging)
     int G = 1;
@@ -891,6 +892,8 @@ void launch_ionic_step(pdg_ctx *c, const double *u, const double *u_prev, double
     a.I = I;
     a.prm = vec(c, c->w.prm);
     a.dt = c->dt;
+    a.ext_now = c->ion_endpoint ? 2.0 : 1.5;
+    a.ext_prev = c->ion_endpoint ? -1.0 : -0.5;
     a.bad = &c->sc[0].ionic_bad;
     HIPCHK(launch_ionic(a, c->stream));
 }
@@ -1297,6 +1300,10 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             c->spmv_wpg = (int)value;
             c->dA.wpg = (int)value;
             drop_graph(c);
+            break;
+        case PDG_OPT_ION_EXTRAPOLATION:
+            if (value != 0 && value != 1) throw Error(PDG_EINVAL, "ion extrapolation must be 0 or 1");
+            c->ion_endpoint = (int)value;
             break;
         case PDG_OPT_LANCZOS_CAP:
             if (value < 1 || value > (1 << 20)) throw Error(PDG_EINVAL, "Lanczos cap must be in 1..2^20");

@@ -167,6 +167,7 @@ struct IonicArgs {
     double *I;
     const double *prm;      // 24 ionic parameters
     double dt;
+    double ext_now, ext_prev;  // u~ = ext_now u^k + ext_prev u^(k-1) in the ion term
     int32_t *bad;           // set to 1 when a concentration <= 0 is met
 };
 

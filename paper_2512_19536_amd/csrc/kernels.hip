@@ -1103,7 +1103,7 @@ __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
                 for (int l = 0; l < 5; ++l) yv[l] = fma(phi[k], s_y[l][k], yv[l]);
             }
             double f;
-            ionic_model(1.5 * u - 0.5 * up, yv, s_prm, f, nullptr, bad);
+            ionic_model(a.ext_now * u + a.ext_prev * up, yv, s_prm, f, nullptr, bad);
             s_w[lane][0] = a.qp_w[q] * f;
 #pragma unroll
             for (int k = 0; k < ND; ++k) s_phi[lane][k] = phi[k];

@@ -76,6 +76,7 @@ class Problem:
     coarse_prec: str = "f64"
     maxit: int = 5000
     elem_ptr: np.ndarray | None = None   # batch of independent systems: element range of each
+    ion_extrap: str = "midpoint"         # potential in the ion term: "midpoint" or "endpoint" (t^(k+1))
 
     @property
     def n_elem(self):

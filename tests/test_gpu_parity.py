@@ -57,6 +57,8 @@ CASES = {
     # than) the subdomains
     "t1_p4_q2": lambda: replace(problems.table1_problem(100, 4, 2), coarse_q=2),
     "3d_p3_q2_own_coarse": lambda: _own_coarse(problems.small3d(n_grid=8, p=3, n_sub=6), 3, q=2),
+    # the other reading of the ion-term extrapolation (to t^(k+1)), at the paper's time step
+    "3d_p2_endpoint": lambda: replace(problems.small3d(n_grid=8, p=2, n_sub=6), dt=0.0025, ion_extrap="endpoint"),
 }
 
 
@@ -124,7 +126,7 @@ def test_schwarz_apply(case):
     assert rel_max(N(z), md.schwarz.apply(r)) < 1e-11
 
 
-@pytest.mark.parametrize("case", ["cfg1", "2d_p4", "3d_p2", "3d_p4"])
+@pytest.mark.parametrize("case", ["cfg1", "2d_p4", "3d_p2", "3d_p4", "3d_p2_endpoint"])
 def test_project_ionic_rhs(case):
     pr, md, ctx = _setup(case)
     U0, _, Y0 = md.initial_state()
@@ -166,7 +168,7 @@ def test_solve(case):
     assert info["relres"] <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["cfg1", "3d_p2", "3d_p3", "t1_p3"])
+@pytest.mark.parametrize("case", ["cfg1", "3d_p2", "3d_p3", "t1_p3", "3d_p2_endpoint"])
 def test_time_steps(case):
     pr, md, ctx = _setup(case)
     nsteps = pr.n_steps if case == "cfg1" else 3

@@ -172,11 +172,14 @@ def test_mass_conservation_without_ionic_terms(cfg1_oracle):
         m0 = mk
 
 
-def test_uniform_state_reduces_to_single_cell_recurrence():
+@pytest.mark.parametrize("reading", ["midpoint", "endpoint"])
+def test_uniform_state_reduces_to_single_cell_recurrence(reading):
     """Spatially uniform data: every element follows the 0-D recurrence
-    y^(k+1) = y^k + dt dy/dt(u^k, y^k); C_m (u^(k+1) - u^k) = -dt f(u~, y^(k+1))."""
+    y^(k+1) = y^k + dt dy/dt(u^k, y^k); C_m (u^(k+1) - u^k) = -dt f(u~, y^(k+1)),
+    with u~ = (3u^k - u^(k-1))/2 (mid-point reading) or 2u^k - u^(k-1)."""
     pr = problems.small2d(n=12, p=1)
     pr.u0_elem[:] = -52.0
+    pr.ion_extrap = reading
     md = Monodomain(pr)
     U, Up, Y = md.initial_state()
     u, up, y = -52.0, -52.0, params.Y_REST.copy()
@@ -184,7 +187,7 @@ def test_uniform_state_reduces_to_single_cell_recurrence():
     for _ in range(5):
         U, Up, Y, info = md.step(U, Up, Y, tol=1e-13)
         ynew = y + pr.dt * ionic.dydt(np.array(u), y, prm)
-        ut = 1.5 * u - 0.5 * up
+        ut = (3.0 * u - up) / 2.0 if reading == "midpoint" else 2.0 * u - up
         unew = u - pr.dt / pr.c_m * ionic.f_ion(np.array(ut), ynew, prm)
         up, u, y = u, float(unew), ynew
         d = md.disc
