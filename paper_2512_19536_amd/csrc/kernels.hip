@@ -292,6 +292,28 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
     const int c_begin = a.wg_c0[wg], c_end = a.wg_c0[wg + 1];
     const int b = a.grp_sys[c_begin];
     DevScalars *sc = a.sc + b;
+    constexpr int NV = NQ > 0 ? NQ : 1;
+    // The thread's first dof (usually its only one) is read before the
+    // reductions below, which do not change it, so the latencies overlap.
+    const int f_e0 = a.grp_ptr[c_begin], f_n = (a.grp_ptr[c_begin + 1] - f_e0) * ND;
+    const bool f_has = (int)threadIdx.x < f_n;
+    int64_t f_idx = 0;
+    double f_r = 0.0, f_p = 0.0, f_q = 0.0, f_x = 0.0, f_P[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) f_P[k] = 0.0;
+    if (f_has) {
+        const int le = threadIdx.x / ND, i = threadIdx.x - le * ND;
+        f_idx = (int64_t)a.grp_elems[f_e0 + le] * ND + i;
+        f_r = a.r[f_idx];
+        if (!a.init) {
+            f_p = a.p[f_idx];
+            f_q = a.q[f_idx];
+            f_x = a.x[f_idx];
+        }
+        if (NQ > 0)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) f_P[j] = a.P[f_idx * NQ + j];
+    }
     // the owner workgroup may set `done` during this launch
     if (block_bcast<128>(threadIdx.x == 0 ? sc->done : 0)) return;
     double alpha = 0.0;
@@ -318,22 +340,41 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
     double rr = 0.0;
     for (int c = c_begin; c < c_end; ++c) {
         const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * ND;
-        constexpr int NV = NQ > 0 ? NQ : 1;
         double v[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] = 0.0;
         for (int d = threadIdx.x; d < ndof; d += 128) {
-            const int le = d / ND, i = d - le * ND;
-            const int64_t idx = (int64_t)a.grp_elems[e0 + le] * ND + i;
-            double rv = a.r[idx];
+            const bool first = c == c_begin && d == (int)threadIdx.x;
+            int64_t idx;
+            double rv, pv = 0.0, qv = 0.0, xv = 0.0, Pr[NV];
+            if (first) {
+                idx = f_idx;
+                rv = f_r;
+                pv = f_p;
+                qv = f_q;
+                xv = f_x;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) Pr[j] = f_P[j];
+            } else {
+                const int le = d / ND, i = d - le * ND;
+                idx = (int64_t)a.grp_elems[e0 + le] * ND + i;
+                rv = a.r[idx];
+                if (!a.init) {
+                    pv = a.p[idx];
+                    qv = a.q[idx];
+                    xv = a.x[idx];
+                }
+                if (NQ > 0)
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) Pr[j] = a.P[idx * NQ + j];
+            }
             if (!a.init) {
-                a.x[idx] = fma(alpha, a.p[idx], a.x[idx]);
-                rv = fma(-alpha, a.q[idx], rv);
+                a.x[idx] = fma(alpha, pv, xv);
+                rv = fma(-alpha, qv, rv);
                 a.r[idx] = rv;
             }
             rr = fma(rv, rv, rr);
             if (NQ > 0) {
-                const double *Pr = a.P + idx * NQ;
 #pragma unroll
                 for (int j = 0; j < NQ; ++j) v[j] = fma(Pr[j], rv, v[j]);
             }
@@ -355,12 +396,12 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
 // Schwarz apply: z_i = K_i^{-1} r_i for every subdomain and z0 = K_0^{-1} r0.
 // Each inverse is symmetric and stored as packed lower-triangular 64x64 tiles
 // (row-major inside a tile).  A workgroup (256 threads) owns one work item:
-// tile columns [j0, j0 + nj) of one 64-row tile row I of one system, using
-// tile (I, J) as stored for J <= I and tile (J, I) transposed for J > I.  Each
-// thread loads 16 bytes per tile row for RPT rows, so every load instruction
-// of a wavefront reads whole contiguous tile rows; the next tile is loaded
-// while the current one is multiplied.  Items hold ~256 KB of tiles, so the
-// grid is many similar-sized workgroups.
+// the stored tiles (I, J), J in [j0, j0 + nj), of one packed tile row I of
+// one system; each tile is read once and used for both of its products
+// (see schwarz_item).  Each thread loads 16 bytes per tile row for RPT rows,
+// so every load instruction of a wavefront reads whole contiguous tile rows.
+// Items hold ~192 KiB of tiles by default, so the grid is many similar-sized
+// workgroups.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename E> struct AccT { using T = float; };
