@@ -108,6 +108,39 @@ def test_error_codes_from_the_host():
     _expect(_lib.PDG_ESTATE, ctx._call, "pdg_bind_workspace", None, 0)
 
 
+def test_option_and_coarse_errors_from_the_host():
+    """Option values out of range, the coarse degree above p, and the workspace
+    growing with the Lanczos history; all on a host-only context."""
+    pr = problems.small2d(n=12, p=2)
+    ctx = solver.Context(None)
+    for opt, val in ((_lib.PDG_OPT_PRECONDITIONER, 2), (_lib.PDG_OPT_LANCZOS_CAP, 0),
+                     (_lib.PDG_OPT_LANCZOS_CAP, (1 << 20) + 1), (_lib.PDG_OPT_ION_EXTRAPOLATION, 2),
+                     (_lib.PDG_OPT_SCHWARZ_ITEM_KB, 16), (_lib.PDG_OPT_SPMV_WAVES, 3), (99, 1)):
+        _expect(_lib.PDG_EINVAL, ctx.set_option, opt, val)
+    for opt in (_lib.PDG_OPT_PRECONDITIONER, _lib.PDG_OPT_ION_EXTRAPOLATION):
+        ctx.set_option(opt, 0)
+        ctx.set_option(opt, 1)
+    ctx.set_mesh(pr.mesh, 2)
+    ctx.assemble(1.0, 1.0, 0.05, 10.0)
+    _expect(_lib.PDG_EINVAL, ctx.setup_preconditioner, pr.elem_sub, None, 3)  # q > p
+    ctx.setup_preconditioner(pr.elem_sub, None, 2)
+    w0 = ctx.workspace_query()
+    ctx.set_option(_lib.PDG_OPT_LANCZOS_CAP, 4096)
+    assert ctx.workspace_query() == w0 + 2048 * 16
+
+
+def test_coarse_system_size_limit():
+    """A coarse system above 16,384 dofs is refused at setup (PDG_EINVAL); the
+    largest Table-1 cell (15,360) is below it."""
+    big = problems.table1_problem(1100, 4, 1)  # 1100 one-element agglomerates x 15 = 16,500 coarse dofs
+    c2 = solver.Context(None)
+    c2.set_mesh(big.mesh, 4)
+    c2.assemble(big.chi_m, big.c_m, big.dt, big.eta0)
+    with pytest.raises(PdgError) as ei:
+        c2.setup_preconditioner(big.elem_sub, big.elem_coarse, 4)
+    assert ei.value.status == _lib.PDG_EINVAL and "16384" in str(ei.value)
+
+
 def test_indefinite_system_reports_not_spd():
     """Without penalty (eta0 = 0) and a negligible mass term the SIPG matrix is
     indefinite, so a subdomain's Cholesky factorisation meets a pivot <= 0."""
