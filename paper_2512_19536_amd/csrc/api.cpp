@@ -57,7 +57,7 @@ struct Ws {
     int itsys, itrow, itj0, itnj, itown, rtit0, dofrt, itdot, rowpart;
     int sysn, sysnt, systoff, sysdof0, syscb, rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
     int grpptr, grpel, upsys, cchunk, csys0, crt0, csys, rspmv, rupd, ritem, rowner;
-    int spwg, upwg, chunk0, lanc;
+    int spwg, upwg, chunk0, lanc, pucr;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
 };
 
@@ -466,6 +466,27 @@ void plan_layout(pdg_ctx *c) {
     w.part = L.add(std::max<int64_t>(1, (int64_t)c->spmv_wg_g0.size()) * 2 * 8);  // SpMV partials
     w.rrpart = L.add(std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8);     // update partials
     w.lanc = L.add((size_t)n_sys * c->lcap * 16);                                 // PCG coefficients
+    w.pucr = L.add(((N + 255) / 256) * 2 * 4);  // coarse range of every p-update block
+}
+
+// Per block of 256 dofs of the p-update: the first coarse element its dofs
+// touch and how many (elements are numbered so that these are few); more than
+// kPupdateKmax marks a block that reads coarse values per dof instead.
+std::vector<int32_t> pupdate_coarse_ranges(const pdg_ctx *c) {
+    const int64_t nd = c->mesh.nd, N = c->mesh.n_elem * nd, nb = (N + 255) / 256;
+    std::vector<int32_t> out(nb * 2, 0);
+    if (c->pc.q <= 0) return out;
+    for (int64_t blk = 0; blk < nb; ++blk) {
+        const int64_t e0 = blk * 256 / nd, e1 = (std::min(N, blk * 256 + 256) - 1) / nd;
+        int32_t lo = c->pc.elem_coarse[e0], hi = lo;
+        for (int64_t e = e0; e <= e1; ++e) {
+            lo = std::min(lo, c->pc.elem_coarse[e]);
+            hi = std::max(hi, c->pc.elem_coarse[e]);
+        }
+        out[2 * blk] = lo;
+        out[2 * blk + 1] = hi - lo + 1 <= kPupdateKmax ? hi - lo + 1 : kPupdateKmax + 1;
+    }
+    return out;
 }
 
 template <class T>
@@ -615,6 +636,7 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, const double *r, Dev
     p.n_elem = c->mesh.n_elem;
     p.P = p.nq0 > 0 ? wptr<double>(c, c->w.P) : nullptr;
     p.elem_coarse = p.nq0 > 0 ? wptr<int32_t>(c, c->w.ecoa) : nullptr;
+    p.blk_crange = wptr<int32_t>(c, c->w.pucr);
     p.elem_sys = wptr<int32_t>(c, c->w.elsys);
     p.dof_rt = wptr<int32_t>(c, c->w.dofrt);
     p.rt_item0 = wptr<int32_t>(c, c->w.rtit0);
@@ -1244,6 +1266,7 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         put_tiles(w.tcoa, pc.inv64.data() + nloc, ncoa, pc.coarse_prec);
         upload(c, w.P, pc.P);
         upload(c, w.ecoa, pc.elem_coarse);
+        upload(c, w.pucr, pupdate_coarse_ranges(c));
         upload(c, w.grpptr, c->grp_ptr);
         upload(c, w.grpel, c->grp_elems);
         upload(c, w.upsys, c->upd_sys);

@@ -129,6 +129,9 @@ struct SchwarzArgs {
 // a tile row, column partials of the stored tiles below it, and P z0) and
 // updates the search direction; in PCG modes it also closes each system's
 // iteration: (r, z), beta, convergence on ||r||^2.
+// Coarse elements whose values a p-update block keeps in LDS.
+constexpr int kPupdateKmax = 8;
+
 struct PupdateArgs {
     int mode;               // 0: out = z; 1: PCG init, p = z; 2: PCG, p = z + beta p
     int pre_rz;             // 1: take (r, z) from sc.rz_sum instead of summing the Schwarz shares
@@ -137,6 +140,8 @@ struct PupdateArgs {
     int64_t n_elem;
     const double *P;
     const int32_t *elem_coarse;  // coarse element of each element (system-contiguous numbering)
+    const int32_t *blk_crange;   // [blocks][2]: first coarse element of the block's dofs and their
+                                 // count, or kPupdateKmax + 1 (coarse values read per dof)
     const int32_t *elem_sys;     // batch system of each element
     const int32_t *dof_rt;       // [N] tile row * 64 + row inside the tile, of every fine dof
     const int32_t *rt_item0;     // [n_rt+1] first item of each tile row

@@ -697,23 +697,14 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const double p_old = (my >= 0 && a.mode == 2) ? a.p[idx] : 0.0;
     // coarse values z0 of the block's coarse elements, once per block: the
     // block's elements usually lie in one or two coarse elements (numbered
-    // contiguously), so the block computes their KMAX * NQ values into LDS
-    constexpr int KMAX = 8;
+    // contiguously), so the block computes their n_c * NQ values into LDS
+    // (the range is planned on the host)
+    constexpr int KMAX = kPupdateKmax;
     __shared__ double s_z0[KMAX * (NQ > 0 ? NQ : 1)];
-    __shared__ int s_cr[2];
     int c_lo = 0, n_c = KMAX + 1;
     if (NQ > 0) {
-        if (threadIdx.x == 0) {
-            s_cr[0] = a.elem_coarse[i0 / nd];
-            s_cr[1] = a.elem_coarse[i1 / nd];
-        }
-        __syncthreads();
-        c_lo = s_cr[0];
-        n_c = s_cr[1] - c_lo + 1;
-        // the range holds every element's coarse element only if it is monotone over the block
-        const int ce = idx < n ? a.elem_coarse[idx / nd] : c_lo;
-        const int bad = __syncthreads_or(ce < c_lo || ce >= c_lo + n_c);
-        if (bad || n_c > KMAX || n_c < 1) n_c = KMAX + 1;
+        c_lo = a.blk_crange[2 * blockIdx.x];
+        n_c = a.blk_crange[2 * blockIdx.x + 1];
         if (n_c <= KMAX) {
             for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
                 const int c = c_lo + t / NQ, j = t % NQ;
