@@ -56,8 +56,8 @@ struct Ws {
     int grows, gslot, gcol, gval, gsys, mass, minv, qpptr, qpxi, qpw, norm, prm, subptr, subel;
     int itsys, itrow, itj0, itnj, itown, rtit0, dofrt, itdot, rowpart;
     int sysn, sysnt, systoff, sysdof0, syscb, rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
-    int grpptr, grpel, upsys, cchunk, csys0, crt0, csys, rspmv, rupd, ritem, rowner;
-    int spwg, upwg, chunk0, lanc, pucr;
+    int grpptr, grpel, upsys, cchunk, csys0, rspmv, rupd, ritem, rowner;
+    int spwg, upwg, chunk0, lanc, pucr, cbase;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
 };
 
@@ -443,8 +443,6 @@ void plan_layout(pdg_ctx *c) {
     w.upsys = L.add(c->upd_sys.size() * 4);
     w.cchunk = L.add(c->cchunk_ptr.size() * 4);
     w.csys0 = L.add((n_sys + 1) * 4);
-    w.crt0 = L.add(n_sys * 4);
-    w.csys = L.add(std::max(pc.n_coarse, 1) * 4);
     w.rspmv = L.add((n_sys + 1) * 4);
     w.rupd = L.add((n_sys + 1) * 4);
     w.ritem = L.add((n_sys + 1) * 4);
@@ -467,6 +465,20 @@ void plan_layout(pdg_ctx *c) {
     w.rrpart = L.add(std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8);     // update partials
     w.lanc = L.add((size_t)n_sys * c->lcap * 16);                                 // PCG coefficients
     w.pucr = L.add(((N + 255) / 256) * 2 * 4);  // coarse range of every p-update block
+    w.cbase = L.add(std::max(pc.n_coarse, 1) * 4);   // coarse values: tile-row position of each coarse element
+}
+
+// For coarse element c of batch system b: 64 * (b's first coarse tile row) +
+// (c's first dof in b's coarse system), so that value j of c sits in tile row
+// (base + j) / 64 at row (base + j) % 64.
+std::vector<int32_t> coarse_value_base(const pdg_ctx *c) {
+    const Precond &pc = c->pc;
+    std::vector<int32_t> out(std::max(pc.n_coarse, 1), 0);
+    if (pc.q <= 0) return out;
+    for (int b = 0; b < c->n_sys; ++b)
+        for (int ce = pc.csys_ce0[b]; ce < pc.csys_ce0[b + 1]; ++ce)
+            out[ce] = 64 * c->coarse_rt0[b] + (ce - pc.csys_ce0[b]) * pc.nq0;
+    return out;
 }
 
 // Per block of 256 dofs of the p-update: the first coarse element its dofs
@@ -637,15 +649,13 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, const double *r, Dev
     p.P = p.nq0 > 0 ? wptr<double>(c, c->w.P) : nullptr;
     p.elem_coarse = p.nq0 > 0 ? wptr<int32_t>(c, c->w.ecoa) : nullptr;
     p.blk_crange = wptr<int32_t>(c, c->w.pucr);
+    p.coarse_base = wptr<int32_t>(c, c->w.cbase);
     p.elem_sys = wptr<int32_t>(c, c->w.elsys);
     p.dof_rt = wptr<int32_t>(c, c->w.dofrt);
     p.rt_item0 = wptr<int32_t>(c, c->w.rtit0);
     p.rt_k = wptr<int32_t>(c, c->w.rtk);
     p.rt_nt = wptr<int32_t>(c, c->w.rtnt);
     p.rt_cbase = wptr<int64_t>(c, c->w.rtcb);
-    p.coarse_rt0 = wptr<int32_t>(c, c->w.crt0);
-    p.csys_ce0 = wptr<int32_t>(c, c->w.csys0);
-    p.coarse_sys = wptr<int32_t>(c, c->w.csys);
     p.part = wptr<double>(c, c->w.rowpart);
     p.colpart = wptr<double>(c, c->w.colp);
     p.itemdot = wptr<double>(c, c->w.itdot);
@@ -1202,14 +1212,7 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.rtk, c->rt_k);
         upload(c, w.rtnt, c->rt_nt);
         upload(c, w.rtcb, c->rt_cbase);
-        upload(c, w.crt0, c->coarse_rt0);
         upload(c, w.csys0, pc.q > 0 ? pc.csys_ce0 : std::vector<int32_t>(c->n_sys + 1, 0));
-        if (pc.q > 0) {
-            std::vector<int32_t> csys(pc.n_coarse);
-            for (int b = 0; b < c->n_sys; ++b)
-                for (int cc = pc.csys_ce0[b]; cc < pc.csys_ce0[b + 1]; ++cc) csys[cc] = b;
-            upload(c, w.csys, csys);
-        }
         upload(c, w.rspmv, c->r_spmv);
         upload(c, w.rupd, c->r_upd);
         upload(c, w.rowner, c->r_owner);
@@ -1267,6 +1270,7 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.P, pc.P);
         upload(c, w.ecoa, pc.elem_coarse);
         upload(c, w.pucr, pupdate_coarse_ranges(c));
+        upload(c, w.cbase, coarse_value_base(c));
         upload(c, w.grpptr, c->grp_ptr);
         upload(c, w.grpel, c->grp_elems);
         upload(c, w.upsys, c->upd_sys);

@@ -147,9 +147,8 @@ struct PupdateArgs {
     const int32_t *rt_item0;     // [n_rt+1] first item of each tile row
     const int32_t *rt_k, *rt_nt; // tile-row index inside its dense system, tile rows of the system
     const int64_t *rt_cbase;     // global tile index of the dense system's first tile
-    const int32_t *coarse_rt0;   // [n_sys] first tile row of each batch system's coarse system
-    const int32_t *csys_ce0;     // [n_sys+1] first coarse element of each batch system
-    const int32_t *coarse_sys;   // [n_coarse] batch system of each coarse element
+    const int32_t *coarse_base;  // [n_coarse] value j of coarse element c: tile row (base + j) / 64,
+                                 // row (base + j) % 64
     const double *part;          // Schwarz row partials
     const double *colpart;       // Schwarz column partials
     const double *itemdot;

@@ -663,12 +663,23 @@ __global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a, int max_nj) {
 // p = z (+ beta p).  In PCG modes every workgroup first forms (r, z) from the
 // items' shares (fixed order) to get beta; workgroup 0 also closes the
 // iteration: ||r||^2 from the update chunks, convergence / breakdown flags.
-__device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) {
+// Where the partials of tile row rt are: its items, its index K inside its
+// dense system, the system's tile rows and first tile.
+struct TileRow {
+    int it0, it1, K, nt;
+    int64_t cb;
+};
+
+__device__ inline TileRow tile_row(const PupdateArgs &a, int rt) {
+    return TileRow{a.rt_item0[rt], a.rt_item0[rt + 1], a.rt_k[rt], a.rt_nt[rt], a.rt_cbase[rt]};
+}
+
+__device__ inline double tile_row_value(const PupdateArgs &a, const TileRow &t, int lane) {
     double v = 0.0;
-    for (int it = a.rt_item0[rt]; it < a.rt_item0[rt + 1]; ++it) v += a.part[(int64_t)it * TILE + lane];
+    for (int it = t.it0; it < t.it1; ++it) v += a.part[(int64_t)it * TILE + lane];
     // column partials of the stored tiles (I, K), I > K, below this tile row
-    const int K = a.rt_k[rt], nt = a.rt_nt[rt];
-    const int64_t cb = a.rt_cbase[rt];
+    const int K = t.K, nt = t.nt;
+    const int64_t cb = t.cb;
     // four independent partial sums (fixed order) so the loads overlap
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
     int I = K + 1;
@@ -680,6 +691,10 @@ __device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) 
     }
     for (; I < nt; ++I) c0 += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
     return v + ((c0 + c1) + (c2 + c3));
+}
+
+__device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) {
+    return tile_row_value(a, tile_row(a, rt), lane);
 }
 
 template <int NQ>
@@ -695,6 +710,14 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     // systems that turn out to be done; those values are dropped) and its
     // memory latency does not add to that of the reductions below.
     const double p_old = (my >= 0 && a.mode == 2) ? a.p[idx] : 0.0;
+    // where this dof's fine value is (static tables, read before the coarse part's barrier)
+    int f_lane = 0;
+    TileRow f_tr{0, 0, 0, 0, 0};
+    if (my >= 0 && !a.r_ident) {
+        const int dr = a.dof_rt[idx];
+        f_lane = dr & 63;
+        f_tr = tile_row(a, dr >> 6);
+    }
     // coarse values z0 of the block's coarse elements, once per block: the
     // block's elements usually lie in one or two coarse elements (numbered
     // contiguously), so the block computes their n_c * NQ values into LDS
@@ -708,9 +731,8 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
         if (n_c <= KMAX) {
             for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
                 const int c = c_lo + t / NQ, j = t % NQ;
-                const int b = a.coarse_sys[c];
-                const int gi = (c - a.csys_ce0[b]) * NQ + j;
-                s_z0[t] = tile_row_value(a, a.coarse_rt0[b] + (gi >> 6), gi & 63);
+                const int gi = a.coarse_base[c] + j;
+                s_z0[t] = tile_row_value(a, gi >> 6, gi & 63);
             }
             __syncthreads();
         }
@@ -720,8 +742,7 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
         if (a.r_ident) {
             zz = a.r_ident[idx];
         } else {
-            const int dr = a.dof_rt[idx];
-            zz = tile_row_value(a, dr >> 6, dr & 63);
+            zz = tile_row_value(a, f_tr, f_lane);
         }
         if (NQ > 0) {
             const int64_t e = idx / nd;
@@ -731,12 +752,11 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
 #pragma unroll
                 for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
             } else {
-                const int g0 = (ce - a.csys_ce0[my]) * NQ;
-                const int rt0 = a.coarse_rt0[my];
+                const int g0 = a.coarse_base[ce];
 #pragma unroll
                 for (int j = 0; j < NQ; ++j) {
                     const int gi = g0 + j;
-                    zz = fma(Pr[j], tile_row_value(a, rt0 + (gi >> 6), gi & 63), zz);
+                    zz = fma(Pr[j], tile_row_value(a, gi >> 6, gi & 63), zz);
                 }
             }
         }
