@@ -626,9 +626,9 @@ def main():
     ap.add_argument("--fig2-p", type=int, default=4, help="fig2: degree p = q")
     ap.add_argument("--fig2-h", type=int, default=4, help="fig2: coarse size H / h")
     ap.add_argument("--fig2-out", default=None, help="fig2: JSON file for iterations and snapshots")
-    ap.add_argument("--epochs", type=int, default=30, help="cfg5: training epochs")
+    ap.add_argument("--epochs", type=int, default=60, help="cfg5: training epochs")
     ap.add_argument("--batch-steps", type=int, default=4, help="cfg5: time steps per training batch")
-    ap.add_argument("--lr", type=float, default=1e-3, help="cfg5: peak learning rate")
+    ap.add_argument("--lr", type=float, default=3e-3, help="cfg5: peak learning rate")
     ap.add_argument("--traj-steps", type=int, default=100, help="cfg5: steps per trajectory")
     ap.add_argument("--train-trajs", type=int, default=0, help="cfg5: use only the first N training trajectories")
     ap.add_argument("--test-trajs", type=int, default=0, help="cfg5: use only the first N held-out trajectories")
