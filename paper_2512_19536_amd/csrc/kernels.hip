@@ -478,9 +478,11 @@ __device__ inline double sys_input(const SchwarzArgs &a, int s, bool coarse, int
 // One work item: stored tiles (I, J), J in [j0, j0 + nj), of packed tile row
 // I of system s (J <= I).  Each tile is read once and used twice:
 //   row use      y_I += T x_J   (accumulated in registers over the item)
-//   column use   y_J  = T^T x_I (J < I; reduced across the row groups with
-//                wave shuffles and one double-buffered LDS exchange, written as
-//                the tile's column partial)
+//   column use   y_J  = T^T x_I (J < I; reduced across the row groups inside
+//                each wavefront with shuffles; each wavefront leaves its sum in
+//                the tile's own LDS slot, and after the last tile one barrier
+//                lets wavefront 0 add the four sums of every tile and write the
+//                tile's column partial, so tiles need no barrier of their own)
 // The first two tiles are requested before x is gathered into LDS so their
 // latency overlaps the gather.  Tiles then stream through two register
 // buffers A and B in a fixed ping-pong (no register copies, no conditional
@@ -508,7 +510,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     double *xI64 = x64 + max_nj * TILE;
     A *xa = sizeof(A) == 8 ? reinterpret_cast<A *>(x64) : reinterpret_cast<A *>(xI64 + TILE);
     A *xIa = xa + max_nj * TILE;
-    A *colx = reinterpret_cast<A *>(smem) + (sizeof(A) == 8 ? 1 : 3) * (max_nj + 1) * TILE;  // [2][4][64]
+    A *colx = reinterpret_cast<A *>(smem) + (sizeof(A) == 8 ? 1 : 3) * (max_nj + 1) * TILE;  // [max_nj][4][64]
     auto tile_ptr = [&](int J) -> const E * {
         return tiles + (toff + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE) + (rg * RPT) * TILE + cg * CW;
     };
@@ -546,7 +548,6 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     }
     __syncthreads();
     double dcol = 0.0;
-    int par = 0;
     // one tile: row use always, column use below the diagonal
     auto tile_step = [&](const V (&buf)[RPT], int jj) {
         const int J = j0 + jj;
@@ -569,23 +570,16 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
             }
         }
         if (J < I) {
-            // sum over the row groups inside the wavefront, then over the 4 wavefronts
+            // sum over the row groups inside the wavefront; the tile's slot
+            // keeps the four wavefronts' sums until after the last tile
 #pragma unroll
             for (int off = NC; off < 64; off <<= 1)
 #pragma unroll
                 for (int c = 0; c < CW; ++c) cacc[c] += __shfl_xor(cacc[c], off, 64);
-            A *cx = colx + par * 4 * TILE;
+            A *cx = colx + jj * 4 * TILE;
             if (lane < NC)
 #pragma unroll
                 for (int c = 0; c < CW; ++c) cx[wv * TILE + cg * CW + c] = cacc[c];
-            __syncthreads();
-            if (tid < TILE) {
-                const double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
-                                 (double)cx[3 * TILE + tid];
-                a.colpart[(cbase + J) * TILE + tid] = v;
-                dcol = fma(x64[jj * TILE + tid], v, dcol);
-            }
-            par ^= 1;
         }
     };
     int jj = 0;
@@ -610,6 +604,16 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         load(bA, j0 + jj);
         tile_step(bA, jj);
     }
+    // column partials of the item's tiles below the diagonal, in tile order
+    __syncthreads();
+    if (tid < TILE)
+        for (int jj2 = 0; jj2 < nj && j0 + jj2 < I; ++jj2) {
+            const A *cx = colx + jj2 * 4 * TILE;
+            const double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
+                             (double)cx[3 * TILE + tid];
+            a.colpart[(cbase + j0 + jj2) * TILE + tid] = v;
+            dcol = fma(x64[jj2 * TILE + tid], v, dcol);
+        }
     *dot_col = dcol;
     __syncthreads();  // the reduction scratch aliases the x buffers
     A *sR = reinterpret_cast<A *>(smem);
@@ -1326,7 +1330,7 @@ static size_t lds_need(size_t acc, size_t scratch, int max_nj) {
     b = (b + 15) & ~(size_t)15;
     const size_t x_end = (acc == 8 ? 1 : 3) * (size_t)(max_nj + 1) * TILE * acc;  // offset of the exchange area
     if (x_end > b) b = x_end;
-    b += 2 * 4 * TILE * acc;
+    b += (size_t)max_nj * 4 * TILE * acc;  // per-tile column sums of the four wavefronts
     return b > scratch ? b : scratch;
 }
 
