@@ -681,20 +681,23 @@ __device__ inline TileRow tile_row(const PupdateArgs &a, int rt) {
 __device__ inline double tile_row_value(const PupdateArgs &a, const TileRow &t, int lane) {
     double v = 0.0;
     for (int it = t.it0; it < t.it1; ++it) v += a.part[(int64_t)it * TILE + lane];
-    // column partials of the stored tiles (I, K), I > K, below this tile row
+    // column partials of the stored tiles (I, K), I > K, below this tile row:
+    // 16 loads per round (those past the last tile row read nothing) into
+    // eight partial sums, added in a fixed order
     const int K = t.K, nt = t.nt;
     const int64_t cb = t.cb;
-    // four independent partial sums (fixed order) so the loads overlap
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int I = K + 1;
-    for (; I + 3 < nt; I += 4) {
-        c0 += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
-        c1 += a.colpart[(cb + (int64_t)(I + 1) * (I + 2) / 2 + K) * TILE + lane];
-        c2 += a.colpart[(cb + (int64_t)(I + 2) * (I + 3) / 2 + K) * TILE + lane];
-        c3 += a.colpart[(cb + (int64_t)(I + 3) * (I + 4) / 2 + K) * TILE + lane];
+    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int I0 = K + 1; I0 < nt; I0 += 16) {
+        double w[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int I = I0 + u;
+            w[u] = I < nt ? a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c[u & 7] += w[u];
     }
-    for (; I < nt; ++I) c0 += a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane];
-    return v + ((c0 + c1) + (c2 + c3));
+    return v + (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
 }
 
 __device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) {
