@@ -346,6 +346,8 @@ def bench_learned(args):
             "frac": round(sw_gbs / HBM_PEAK_GBS, 4),
             "traffic": None,
             "avg_launch_us": round(t_l / max(n_l, 1) * 1e3, 2),
+            "algorithmic_bytes_per_launch": int(by_l / max(n_l, 1)),
+            "fits_in_256MB_MALL": bool(by_l / max(n_l, 1) < 256e6),
         },
         "mlp_training_roofline": {
             "kernel": "one training step (BF16 MFMA layer products, loss, bias gradients, split sums, Adam)",
@@ -449,10 +451,19 @@ def bench_table1(args):
             kappas.append(ctx.lanczos()[0])  # outside the timed part
         dofs_steps += pr.n_dof * n_steps
         solve_s += dt
+        # kappa from one solve with a seeded random right-hand side (all
+        # eigenvectors present, so the extreme Ritz values converge) from x0 = 0
+        gen = torch.Generator(device=dev).manual_seed(pr.n_dof)
+        b = torch.randn(pr.n_dof, dtype=torch.float64, device=dev, generator=gen)
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()  # b and x come from torch's stream; the solve runs on the context's
+        info_r = ctx.solve(b, x, pr.tol, 40000)
+        kappa_r = ctx.lanczos()[0]
         del ctx
         torch.cuda.empty_cache()
         return {"iters_mean": float(np.mean(iters)), "iters_first": iters[0], "iters_last": iters[-1],
                 "kappa_mean": float(np.mean(kappas)), "kappa_last_step": kappas[-1],
+                "kappa_random_rhs": kappa_r, "iters_random_rhs": info_r["iters"],
                 "ms_per_step": dt * 1e3 / n_steps, "setup_s": round(t_setup, 2)}
 
     for p in ps:
@@ -482,7 +493,8 @@ def bench_table1(args):
     # markdown summary: ours (paper)
     lines = []
     for p in ps:
-        lines.append(f"p = q = {p}: kappa estimate (mean over steps) / mean iterations per step, this library (paper)")
+        lines.append(f"p = q = {p}: kappa estimate (mean over steps) [from a random right-hand side] / "
+                     f"mean iterations per step, this library (paper)")
         lines.append("| row | " + " | ".join(f"N_h={nh}" for nh in nhs) + " |")
         lines.append("|---|" + "---|" * len(nhs))
         for row in [f"H={k}h" for k in ks] + ["CG"]:
@@ -492,7 +504,7 @@ def bench_table1(args):
                 if "error" in c:
                     out.append("n/a")
                     continue
-                txt = f"{c['kappa_mean']:.4g} / {c['iters_mean']:.1f}"
+                txt = f"{c['kappa_mean']:.4g} [{c['kappa_random_rhs']:.4g}] / {c['iters_mean']:.1f}"
                 if "paper" in c:
                     txt += f" ({c['paper']['kappa']:.4g} / {c['paper']['iters']})"
                 out.append(txt)
@@ -636,7 +648,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=4, help="PCG iterations between host polls")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--local-prec", default=None, choices=["f64", "f32", "bf16"])
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle time steps in the CPU baseline (about 7 s each at cfg2)")
     ap.add_argument("--item-kb", type=int, default=None, help="Schwarz work-item size (KiB of tiles)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=1024)
@@ -702,14 +714,18 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     iters = []
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     ev0.record(stream)
     for k in range(args.steps):
+        step_ev[k].record(stream)
         info = ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
         iters.append(info["iters"])
+    step_ev[args.steps].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
+    ms_steps = [step_ev[k].elapsed_time(step_ev[k + 1]) for k in range(args.steps)]
     if args.graph:
         ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 1)
         for _ in range(2):
@@ -722,13 +738,22 @@ def main():
     log(f"[bench] schwarz apply: {n_launch} launches, avg {k_avg_ms * 1e3:.1f} us, {k_bytes / 1e6:.1f} MB "
         f"-> {achieved:.0f} GB/s")
 
-    # plain copy of known size, for calibrating HBM byte counters in profiles
+    # plain copy of known size, for calibrating HBM byte counters in profiles,
+    # then timed: the copy ceiling (bytes read + written per second) on this machine
     nb = args.copy_calibration_mb * (1 << 20)
     src = torch.empty(nb // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     src.fill_(1.0)
     dst.copy_(src)
     torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(3):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nb * 3 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    log(f"[bench] device copy of {nb >> 20} MiB: {copy_gbs:.0f} GB/s (read + write)")
     del src, dst
 
     # precision form: error per step against the same steps taken with FP64
@@ -766,6 +791,9 @@ def main():
         "traffic": traffic,
         "algorithmic_bytes_per_launch": int(k_bytes),
         "avg_launch_us": round(k_avg_ms * 1e3, 2),
+        "copy_ceiling_gb_s": round(copy_gbs, 1),
+        "frac_of_copy_ceiling": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
+        "fits_in_256MB_MALL": bool(k_bytes < 256e6),
     }
     cpu = None
     if not args.no_cpu_baseline:
@@ -794,6 +822,7 @@ def main():
             "n_dof": pr.n_dof, "n_elem": pr.n_elem, "p": pr.p, "n_sub": pr.n_sub,
         },
         "pcg_iters": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
+        "ms_per_step_median": round(float(np.median(ms_steps)), 4),
         "precision_form_error": prec_err,
         "roofline": roof,
         "cpu_baseline": cpu,
