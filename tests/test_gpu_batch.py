@@ -181,3 +181,28 @@ def test_batch_zero_rhs_system_and_statuses():
     assert e.value.status == _lib.PDG_ENOCONV
     assert ctx.system_info(0)["status"] == _lib.PDG_ENOCONV
     assert ctx.system_info(1)["status"] == _lib.PDG_OK  # zero right-hand side
+
+
+@pytest.mark.parametrize("precond", [1, 0])
+def test_batch_lanczos_and_plain_cg_match_single_contexts(precond):
+    """Per-system Lanczos estimates (and the recorded PCG coefficients) of a
+    batch equal those of each system in a context of its own, bitwise, with the
+    Schwarz preconditioner and with none (B = I, plain CG)."""
+    systems = same_degree_systems()
+    bp = problems.concat_problems("batch", systems)
+    opts = {_lib.PDG_OPT_PRECONDITIONER: precond, _lib.PDG_OPT_LANCZOS_CAP: 4096}
+    cb = solver.from_problem(bp, device=DEV, options=opts)
+    U, Up, Y = solver.initial_state(cb, bp)
+    cb.step(U, Up, Y, None, bp.tol, 4000)
+    for s, q in enumerate(systems):
+        c1 = solver.from_problem(q, device=DEV, options=opts)
+        u1, up1, y1 = solver.initial_state(c1, q)
+        info = c1.step(u1, up1, y1, None, q.tol, 4000)
+        assert cb.system_info(s)["iters"] == info["iters"]
+        k_b, lo_b, hi_b = cb.lanczos(s)
+        k_1, lo_1, hi_1 = c1.lanczos(0)
+        a_b, b_b = cb.pcg_coefficients(s, 4096)
+        a_1, b_1 = c1.pcg_coefficients(0, 4096)
+        print(f"[batch] precond {precond} system {s}: iters {info['iters']} kappa {k_b:.6g}", flush=True)
+        assert np.array_equal(a_b, a_1) and np.array_equal(b_b, b_1)
+        assert (k_b, lo_b, hi_b) == (k_1, lo_1, hi_1)
