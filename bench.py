@@ -551,7 +551,7 @@ def bench_fig2(args):
 
     dev = "cuda:0"
     n_steps = args.fig2_steps
-    pr = problems.table1_problem(args.fig2_nh, args.fig2_p, args.fig2_h, n_steps=n_steps)
+    pr = problems.table1_problem(args.fig2_nh, args.fig2_p, args.fig2_h, n_steps=n_steps, chi_cm=args.fig2_chi_cm)
     log(f"[fig2] {pr.name}: {pr.n_elem} elements, {pr.n_dof} dofs, {int(pr.elem_coarse.max()) + 1} agglomerates")
     stream = torch.cuda.Stream(device=dev)
     ctx = from_problem(pr, device=dev, options={_lib.PDG_OPT_GRAPH: 1, _lib.PDG_OPT_CHUNK: 16}, stream=stream)
@@ -613,7 +613,8 @@ def bench_fig2(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{pr.name}: {pr.n_dof} dofs, q = p coarse on H = {args.fig2_h}h agglomerates, "
-                               f"relres 1e-9, {n_steps} steps of 2.5 us, graph replay"},
+                               f"chi_m C_m = {pr.chi_m * pr.c_m:g}, relres 1e-9, {n_steps} steps of 2.5 us, "
+                               f"graph replay"},
         "pcg_iters": {"mean": float(np.mean(iters)), "first": iters[0], "last": iters[-1],
                       "mean_per_1000_steps": [float(np.mean(iters[i:i + 1000])) for i in range(0, n_steps, 1000)]},
         "snapshots": [{k: v for k, v in sn.items() if k != "map"} for sn in snaps],
@@ -638,6 +639,8 @@ def main():
     ap.add_argument("--fig2-p", type=int, default=4, help="fig2: degree p = q")
     ap.add_argument("--fig2-h", type=int, default=4, help="fig2: coarse size H / h")
     ap.add_argument("--fig2-out", default=None, help="fig2: JSON file for iterations and snapshots")
+    ap.add_argument("--fig2-chi-cm", type=float, default=None,
+                    help="fig2: chi_m C_m (default: the Table-1 calibration)")
     ap.add_argument("--epochs", type=int, default=60, help="cfg5: training epochs")
     ap.add_argument("--batch-steps", type=int, default=4, help="cfg5: time steps per training batch")
     ap.add_argument("--lr", type=float, default=3e-3, help="cfg5: peak learning rate")
