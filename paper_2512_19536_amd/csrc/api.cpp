@@ -1101,14 +1101,26 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         c->r_owner.assign(c->n_sys, 0);
         for (int b = 0; b < c->n_sys; ++b) c->r_owner[b] = (int32_t)(c->sys_elem_ptr[b] * c->mesh.nd / 256);
         choose_reductions(c);
-        // algorithmic bytes of one Schwarz apply: stored tiles + input gathers + outputs
-        int64_t lt = 0, ctl = 0;
-        for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx)
-            ((int)sidx < c->pc.n_sub ? lt : ctl) += c->pc.sys[sidx].nt * (c->pc.sys[sidx].nt + 1) / 2;
+        // algorithmic bytes of one Schwarz apply: the tiles below the diagonal in
+        // full, of each diagonal tile the 16-byte pieces that reach its diagonal,
+        // input gathers and outputs
+        auto diag_bytes = [](int prec) {
+            const int cw = 16 / (int)tile_elem_bytes(prec);
+            int64_t pieces = 0;
+            for (int r = 0; r < kTile; ++r) pieces += r / cw + 1;
+            return pieces * 16;
+        };
+        int64_t lt = 0, ctl = 0, ld = 0, cd = 0;
+        for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx) {
+            const int64_t nt = c->pc.sys[sidx].nt;
+            ((int)sidx < c->pc.n_sub ? lt : ctl) += nt * (nt - 1) / 2;
+            ((int)sidx < c->pc.n_sub ? ld : cd) += nt;
+        }
         const int64_t N = c->mesh.n_elem * c->mesh.nd;
         c->schwarz_bytes = lt * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.local_prec) +
-                           ctl * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.coarse_prec) + 3 * N * 8 +
-                           3 * std::max<int64_t>(c->pc.N0, 0) * 8;
+                           ld * diag_bytes(c->pc.local_prec) +
+                           ctl * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.coarse_prec) +
+                           cd * diag_bytes(c->pc.coarse_prec) + 3 * N * 8 + 3 * std::max<int64_t>(c->pc.N0, 0) * 8;
         c->state = S_PRECOND;
     });
 }

@@ -476,7 +476,9 @@ __device__ inline double sys_input(const SchwarzArgs &a, int s, bool coarse, int
 }
 
 // One work item: stored tiles (I, J), J in [j0, j0 + nj), of packed tile row
-// I of system s (J <= I).  Each tile is read once and used twice:
+// I of system s (J <= I).  Each tile is read once and used twice (the
+// diagonal tile (I, I), symmetric, only up to its diagonal: its lower part
+// serves the row use and, transposed, the part above the diagonal):
 //   row use      y_I += T x_J   (accumulated in registers over the item)
 //   column use   y_J  = T^T x_I (J < I; reduced across the row groups inside
 //                each wavefront with shuffles; each wavefront leaves its sum in
@@ -515,12 +517,16 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         return tiles + (toff + (int64_t)I * (I + 1) / 2 + J) * (TILE * TILE) + (rg * RPT) * TILE + cg * CW;
     };
     // Tiles are read once per apply and exceed the last-level cache: non-temporal
-    // loads keep them from evicting data that is reused (the SpMV matrix).
+    // loads keep them from evicting data that is reused (the SpMV matrix).  Of
+    // the diagonal tile only the 16-byte pieces that reach the diagonal are read.
     auto load = [&](V (&buf)[RPT], int J) {
         const E *tp = tile_ptr(J);
+        const bool diag = J == I;
 #pragma unroll
         for (int k = 0; k < RPT; ++k)
-            buf[k] = __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + k * TILE)));
+            buf[k] = (!diag || cg * CW <= rg * RPT + k)
+                         ? __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + k * TILE)))
+                         : __builtin_bit_cast(V, u32x4{0u, 0u, 0u, 0u});
     };
     A accR[RPT];
 #pragma unroll
@@ -548,7 +554,8 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     }
     __syncthreads();
     double dcol = 0.0;
-    // one tile: row use always, column use below the diagonal
+    // one tile: row use and column use; on the diagonal tile the row use takes
+    // the entries up to the diagonal and the column use those below it
     auto tile_step = [&](const V (&buf)[RPT], int jj) {
         const int J = j0 + jj;
         const A *xJ = (sizeof(A) == 8 ? reinterpret_cast<const A *>(x64) : xa) + jj * TILE;
@@ -559,28 +566,41 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
             xb[c] = xJ[cg * CW + c];
             cacc[c] = 0;
         }
+        if (J < I) {
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const A xr = xIv[rg * RPT + k];
+            for (int k = 0; k < RPT; ++k) {
+                const A xr = xIv[rg * RPT + k];
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                const A t = (A)Ld<E>::get(buf[k], c);
-                accR[k] = fma(t, xb[c], accR[k]);
-                cacc[c] = fma(t, xr, cacc[c]);
+                for (int c = 0; c < CW; ++c) {
+                    const A t = (A)Ld<E>::get(buf[k], c);
+                    accR[k] = fma(t, xb[c], accR[k]);
+                    cacc[c] = fma(t, xr, cacc[c]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int r = rg * RPT + k;
+                const A xr = xIv[r];
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const int col = cg * CW + c;
+                    const A t = (A)Ld<E>::get(buf[k], c);
+                    accR[k] = fma(col <= r ? t : (A)0, xb[c], accR[k]);
+                    cacc[c] = fma(col < r ? t : (A)0, xr, cacc[c]);
+                }
             }
         }
-        if (J < I) {
-            // sum over the row groups inside the wavefront; the tile's slot
-            // keeps the four wavefronts' sums until after the last tile
+        // sum over the row groups inside the wavefront; the tile's slot keeps
+        // the four wavefronts' sums until after the last tile
 #pragma unroll
-            for (int off = NC; off < 64; off <<= 1)
+        for (int off = NC; off < 64; off <<= 1)
 #pragma unroll
-                for (int c = 0; c < CW; ++c) cacc[c] += __shfl_xor(cacc[c], off, 64);
-            A *cx = colx + jj * 4 * TILE;
-            if (lane < NC)
+            for (int c = 0; c < CW; ++c) cacc[c] += __shfl_xor(cacc[c], off, 64);
+        A *cx = colx + jj * 4 * TILE;
+        if (lane < NC)
 #pragma unroll
-                for (int c = 0; c < CW; ++c) cx[wv * TILE + cg * CW + c] = cacc[c];
-        }
+            for (int c = 0; c < CW; ++c) cx[wv * TILE + cg * CW + c] = cacc[c];
     };
     int jj = 0;
     if (npair > 0) {
@@ -604,15 +624,21 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         load(bA, j0 + jj);
         tile_step(bA, jj);
     }
-    // column partials of the item's tiles below the diagonal, in tile order
+    // column partials of the item's tiles below the diagonal, in tile order;
+    // the diagonal tile's belong to this item's own rows
     __syncthreads();
+    double diag_add = 0.0;
     if (tid < TILE)
-        for (int jj2 = 0; jj2 < nj && j0 + jj2 < I; ++jj2) {
+        for (int jj2 = 0; jj2 < nj; ++jj2) {
             const A *cx = colx + jj2 * 4 * TILE;
             const double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
                              (double)cx[3 * TILE + tid];
-            a.colpart[(cbase + j0 + jj2) * TILE + tid] = v;
-            dcol = fma(x64[jj2 * TILE + tid], v, dcol);
+            if (j0 + jj2 < I) {
+                a.colpart[(cbase + j0 + jj2) * TILE + tid] = v;
+                dcol = fma(x64[jj2 * TILE + tid], v, dcol);
+            } else {
+                diag_add = v;
+            }
         }
     *dot_col = dcol;
     __syncthreads();  // the reduction scratch aliases the x buffers
@@ -625,7 +651,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         A y = 0;
         const int arg = ar / RPT, ak = ar % RPT;
         for (int c = 0; c < NC; ++c) y += sR[(arg * NC + c) * RPT + ak];
-        yout[ar] = (double)y;
+        yout[ar] = (double)y + diag_add;
     }
     __syncthreads();
 }
