@@ -1101,26 +1101,24 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         c->r_owner.assign(c->n_sys, 0);
         for (int b = 0; b < c->n_sys; ++b) c->r_owner[b] = (int32_t)(c->sys_elem_ptr[b] * c->mesh.nd / 256);
         choose_reductions(c);
-        // algorithmic bytes of one Schwarz apply: the tiles below the diagonal in
-        // full, of each diagonal tile the 16-byte pieces that reach its diagonal,
-        // input gathers and outputs
-        auto diag_bytes = [](int prec) {
-            const int cw = 16 / (int)tile_elem_bytes(prec);
-            int64_t pieces = 0;
-            for (int r = 0; r < kTile; ++r) pieces += r / cw + 1;
-            return pieces * 16;
-        };
-        int64_t lt = 0, ctl = 0, ld = 0, cd = 0;
+        // algorithmic bytes of one Schwarz apply: the rows of the stored tiles
+        // that hold dofs (the last tile row of a system is zero-padded), below
+        // the diagonal in full and of each diagonal tile the 16-byte pieces that
+        // reach its diagonal; plus input gathers and outputs
+        int64_t tile_bytes = 0;
         for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx) {
-            const int64_t nt = c->pc.sys[sidx].nt;
-            ((int)sidx < c->pc.n_sub ? lt : ctl) += nt * (nt - 1) / 2;
-            ((int)sidx < c->pc.n_sub ? ld : cd) += nt;
+            const DenseSys &S = c->pc.sys[sidx];
+            const int64_t es = (int64_t)tile_elem_bytes((int)sidx < c->pc.n_sub ? c->pc.local_prec : c->pc.coarse_prec);
+            const int cw = (int)(16 / es);
+            for (int64_t I = 0; I < S.nt; ++I) {
+                const int rows = (int)std::min<int64_t>(kTile, S.n - I * kTile);
+                int64_t diag_pieces = 0;
+                for (int r = 0; r < rows; ++r) diag_pieces += r / cw + 1;
+                tile_bytes += I * rows * kTile * es + diag_pieces * 16;
+            }
         }
         const int64_t N = c->mesh.n_elem * c->mesh.nd;
-        c->schwarz_bytes = lt * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.local_prec) +
-                           ld * diag_bytes(c->pc.local_prec) +
-                           ctl * kTile * kTile * (int64_t)tile_elem_bytes(c->pc.coarse_prec) +
-                           cd * diag_bytes(c->pc.coarse_prec) + 3 * N * 8 + 3 * std::max<int64_t>(c->pc.N0, 0) * 8;
+        c->schwarz_bytes = tile_bytes + 3 * N * 8 + 3 * std::max<int64_t>(c->pc.N0, 0) * 8;
         c->state = S_PRECOND;
     });
 }

@@ -518,15 +518,19 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     };
     // Tiles are read once per apply and exceed the last-level cache: non-temporal
     // loads keep them from evicting data that is reused (the SpMV matrix).  Of
-    // the diagonal tile only the 16-byte pieces that reach the diagonal are read.
+    // the diagonal tile only the 16-byte pieces that reach the diagonal are read,
+    // and rows past the system's last dof (zero padding) are not read at all.
+    const int rows_left = n - I * TILE;
     auto load = [&](V (&buf)[RPT], int J) {
         const E *tp = tile_ptr(J);
         const bool diag = J == I;
 #pragma unroll
-        for (int k = 0; k < RPT; ++k)
-            buf[k] = (!diag || cg * CW <= rg * RPT + k)
+        for (int k = 0; k < RPT; ++k) {
+            const int r = rg * RPT + k;
+            buf[k] = (r < rows_left && (!diag || cg * CW <= r))
                          ? __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + k * TILE)))
                          : __builtin_bit_cast(V, u32x4{0u, 0u, 0u, 0u});
+        }
     };
     A accR[RPT];
 #pragma unroll
