@@ -10,8 +10,14 @@ coarse space on them, planar stimulus, plain FP64.
 ``--workload cfg4`` runs the batching form instead: 64 independent systems
 (~1.05M dofs, p = 1..4) in one context per degree, each on its own stream,
 stepped together (pdg_step_batch) with PCG chunks replayed as captured graphs.
+``cfg3`` is the precision form (64^3 cubes, p = 3, FP32 Schwarz solves, FP64
+CG), ``cfg5`` the learned initial guess (trained here on the GPU, evaluated on
+held-out steps), ``table1`` the paper's Table-1 experiment (2-D grey/white
+square, iterations and condition numbers per fine/coarse mesh pair) and
+``fig2`` a 4000-step run of its p = 4 problem.
 
-Prints one JSON line (see the design doc for the fields).  Inputs are resident in
+Prints one JSON line: the metric, time per step, iterations, a roofline record
+for the dominant kernel and the oracle's CPU baseline.  Inputs are resident in
 HBM before the timed region starts.
 """
 from __future__ import annotations
@@ -660,7 +666,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; a multi-GPU run is not provided "
-              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+              "(the path would shard by subdomain, with one halo exchange per SpMV and an "
+              "all-reduce of the coarse residual).", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "cfg4":
