@@ -665,7 +665,7 @@ def main():
                     help="precision form: steps also taken with FP64 Schwarz solves to report the error")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; a multi-GPU run is not provided "
+        print("bench.py: this benchmark runs on one GPU only; a multi-GPU run is not provided "
               "(the path would shard by subdomain, with one halo exchange per SpMV and an "
               "all-reduce of the coarse residual).", file=sys.stderr)
         sys.exit(2)
