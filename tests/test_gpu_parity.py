@@ -57,9 +57,25 @@ CASES = {
     # than) the subdomains
     "t1_p4_q2": lambda: replace(problems.table1_problem(100, 4, 2), coarse_q=2),
     "3d_p3_q2_own_coarse": lambda: _own_coarse(problems.small3d(n_grid=8, p=3, n_sub=6), 3, q=2),
+    # subdomains of exactly 64 dofs (one full tile, no padding) and of 128 dofs
+    "3d_p1_tile64": lambda: _blocks_of(problems.small3d(n_grid=8, p=1, n_sub=4), (16, 32)),
     # the other reading of the ion-term extrapolation (to t^(k+1)), at the paper's time step
     "3d_p2_endpoint": lambda: replace(problems.small3d(n_grid=8, p=2, n_sub=6), dt=0.0025, ion_extrap="endpoint"),
 }
+
+
+def _blocks_of(pr, sizes):
+    """The problem with subdomains of consecutive elements, cycling through the
+    given element counts (the last one takes the rest)."""
+    n = pr.n_elem
+    sub = np.zeros(n, dtype=np.int32)
+    e, k = 0, 0
+    while e < n:
+        m = sizes[k % len(sizes)]
+        sub[e:e + m] = k
+        e += m
+        k += 1
+    return replace(pr, elem_sub=sub, elem_coarse=sub.copy())
 
 
 def _own_coarse(pr, n_coarse, q):
