@@ -254,10 +254,18 @@ void build_group_ell(pdg_ctx *c) {
                     blk = &c->K.val[k * nd * nd];
                 }
                 c->grp_col[(s0 + s) * G + r] = col;
-                if (blk)
+                if (!blk) continue;
+                if (nd >= kWideMinNd) {  // G = 1, chunked trial-index-major (kernels.h)
+                    const int64_t c0 = s - s % kWideChunk, sl = s - c0;
+                    const int64_t nch = std::min<int64_t>(kWideChunk, ns - c0);
+                    for (int j = 0; j < nd; ++j)
+                        for (int i = 0; i < nd; ++i)
+                            c->grp_val[(s0 + c0) * nd * nd + j * nch * nd + sl * nd + i] = blk[i * nd + j];
+                } else {
                     for (int j = 0; j < nd; ++j)
                         for (int i = 0; i < nd; ++i)
                             c->grp_val[(s0 + s) * G * nd * nd + (j * G + r) * nd + i] = blk[i * nd + j];
+                }
             }
         }
     }

@@ -36,6 +36,15 @@ struct DevScalars {
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_ZERO_RHS = 2, ST_NOCONV = -5, ST_BREAKDOWN = -6, ST_NONFINITE = -7 };
 
+// Element blocks of more than 32 rows (one element row per SpMV group) are
+// stored in chunks of this many consecutive slots of a row, and inside a
+// chunk trial-index major: value (slot c0 + sl, trial j, test i) of a group
+// whose slots start at s0 sits at
+//   (s0 + c0) * nd * nd + j * (nch * nd) + sl * nd + i,   nch = slots in the chunk,
+// so for each j the chunk's (slot, test) pairs are one contiguous run.
+constexpr int kWideChunk = 16;
+constexpr int kWideMinNd = 33;
+
 // Per-system ranges of the partial-sum producers (workgroups of the SpMV,
 // update and Schwarz kernels, one partial each): system s owns [x[s], x[s+1]).
 struct SysRanges {

@@ -223,14 +223,16 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
 
 // Blocks of more than 32 rows (3-D, p = 4: nd = 35) give one element row per
 // group, and the mapping above would leave 29 of 64 lanes idle.  Here the
-// (slot, row) pairs of the group's blocks are laid end to end and each lane
-// takes one pair per step: for every trial index j a wavefront's load then
-// covers 64 consecutive pairs (at most two contiguous runs of the slot-major
-// layout).  Each pair's dot product goes to LDS, and lane i of wave 0 adds
-// row i's products in slot order, so the result does not depend on WPG.
+// (slot, row) pairs of a chunk of the group's blocks are laid end to end and
+// each lane takes one pair per step; the chunk is stored trial-index major
+// (kWideChunk), so for every trial index j a wavefront's load reads 64
+// consecutive doubles.  Each pair's dot product goes to LDS, and lane i of
+// wave 0 adds row i's products in slot order, so the result does not depend
+// on WPG.
 template <int ND, int WPG, bool NT>
 __global__ __launch_bounds__(64 * WPG) void k_spmv_wide(DevMatrix A, SpmvArgs a) {
-    constexpr int CH = 16;  // slots per LDS chunk
+    static_assert(ND >= kWideMinNd, "chunked layout is built for nd >= kWideMinNd only");
+    constexpr int CH = kWideChunk;  // slots per chunk (and per LDS pass)
     constexpr int T = CH * ND;
     constexpr int STEPS = (T + 63) / 64;
     __shared__ double s_p[T];
@@ -253,11 +255,11 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv_wide(DevMatrix A, SpmvArgs a)
                 const int col = colp[c0 + sl];
                 double sum = 0.0;
                 if (col >= 0) {
-                    const double *vs = vp + (c0 + sl) * ND * ND + i;
+                    const double *vs = vp + c0 * ND * ND + t;
                     const double *xb = a.x + (int64_t)col * ND;
                     double v[ND];
 #pragma unroll
-                    for (int j = 0; j < ND; ++j) v[j] = NT ? __builtin_nontemporal_load(vs + j * ND) : vs[j * ND];
+                    for (int j = 0; j < ND; ++j) v[j] = NT ? __builtin_nontemporal_load(vs + j * tn) : vs[j * tn];
 #pragma unroll
                     for (int j = 0; j < ND; ++j) sum = fma(v[j], xb[j], sum);
                 }
@@ -1279,7 +1281,7 @@ __global__ void k_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit
 // launchers
 template <int ND, int WPG>
 static hipError_t spmv_nd_w(const DevMatrix &A, const SpmvArgs &a, hipStream_t s) {
-    if constexpr (ND > 32) {
+    if constexpr (ND >= kWideMinNd) {
         if (A.nt)
             hipLaunchKernelGGL((k_spmv_wide<ND, WPG, true>), dim3((unsigned)A.n_wg), dim3(64 * WPG), 0, s, A, a);
         else

@@ -109,6 +109,13 @@ def agglomerated_cube_mesh(n: int, length: float, seed: int, target: int = 8,
     contiguous in memory).
     """
     owner = agglomerate_grid(n, seed, target, region_of_cube, min_keep=min(min_keep, target))
+    return cube_mesh_from_owner(owner, n, length, region_of_cube, elem_order)
+
+
+def cube_mesh_from_owner(owner, n: int, length: float, region_of_cube=None, elem_order=None) -> Mesh:
+    """Polyhedral mesh of [0, length]^3 whose element e is the union of the
+    cubes c of an n^3 grid (C order) with ``owner[c] == e`` (ids 0..n_el-1)."""
+    owner = np.asarray(owner, dtype=np.int64)
     h = length / n
     nc = n ** 3
     i, j, k = np.unravel_index(np.arange(nc), (n, n, n))

@@ -50,7 +50,7 @@ import numpy as np
 
 from . import params
 from .mesh2d import voronoi_mesh
-from .mesh3d import agglomerated_cube_mesh, renumber_elements
+from .mesh3d import agglomerated_cube_mesh, cube_mesh_from_owner, renumber_elements
 from .meshdata import Mesh, concat_meshes
 from .partition import order_by_part, quadrants, rcb
 
@@ -153,6 +153,12 @@ def _cube_problem(name, n_grid, length, seed_mesh, seed_part, n_sub, p, spread,
     k = np.unravel_index(np.arange(nc), (n_grid,) * 3)[2]
     region_cube = (k < n_grid // 2).astype(np.int64) if sigma_kind == "two_region" else np.zeros(nc, np.int64)
     mesh = agglomerated_cube_mesh(n_grid, length, seed_mesh, target=target, region_of_cube=region_cube)
+    return _problem_on_cube_mesh(name, mesh, seed_part, n_sub, p, spread, sigma_kind, n_steps,
+                                 seed_fibre, white_ratio, sigma0, sigma_ratio, dt)
+
+
+def _problem_on_cube_mesh(name, mesh, seed_part, n_sub, p, spread, sigma_kind, n_steps, seed_fibre,
+                          white_ratio, sigma0, sigma_ratio, dt) -> Problem:
     cen = mesh.element_centroid()
     part = rcb(cen, n_sub, region=mesh.region, spread=spread, seed=seed_part)
     perm = order_by_part(part, cen)
@@ -204,6 +210,24 @@ def cfg3() -> Problem:
 def small3d(n_grid=6, p=2, n_sub=4, seed=11) -> Problem:
     return _cube_problem(f"small3d_{n_grid}_p{p}", n_grid, 1.0, seed_mesh=seed, seed_part=seed + 1,
                          n_sub=n_sub, p=p, spread=0.3, sigma_kind="two_region", n_steps=3)
+
+
+def slab3d(n_grid=4, p=4, n_sub=3, seed=21) -> Problem:
+    """A 3-D test mesh with one element of many neighbours: the cubes of the
+    grid's second x-layer form one plate element, every other cube is an
+    element of its own, so the plate borders 2 n_grid^2 elements (33 blocks in
+    its matrix row at n_grid = 4)."""
+    nc = n_grid ** 3
+    i = np.unravel_index(np.arange(nc), (n_grid,) * 3)[0]
+    plate = i == 1
+    owner = np.empty(nc, dtype=np.int64)
+    owner[plate] = 0
+    owner[~plate] = 1 + np.arange(int((~plate).sum()))
+    k = np.unravel_index(np.arange(nc), (n_grid,) * 3)[2]
+    region_cube = np.where(plate, 0, (k >= n_grid // 2).astype(np.int64))
+    mesh = cube_mesh_from_owner(owner, n_grid, 1.0, region_of_cube=region_cube)
+    return _problem_on_cube_mesh(f"slab3d_{n_grid}_p{p}", mesh, seed, n_sub, p, 0.3, "two_region", 3,
+                                 None, 3.0, 1.0, 10.0, 0.05)
 
 
 def small2d(n=24, p=2, seed=5) -> Problem:

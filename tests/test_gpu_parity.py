@@ -57,6 +57,9 @@ CASES = {
     # than) the subdomains
     "t1_p4_q2": lambda: replace(problems.table1_problem(100, 4, 2), coarse_q=2),
     "3d_p3_q2_own_coarse": lambda: _own_coarse(problems.small3d(n_grid=8, p=3, n_sub=6), 3, q=2),
+    # a plate element with 32 neighbours: its matrix row spans three chunks
+    # (16 + 16 + 1 blocks) of the layout for blocks of more than 32 rows
+    "3d_p4_slab": lambda: problems.slab3d(n_grid=4, p=4, n_sub=3),
     # subdomains of exactly 64 dofs (one full tile, no padding) and of 128 dofs
     "3d_p1_tile64": lambda: _blocks_of(problems.small3d(n_grid=8, p=1, n_sub=4), (16, 32)),
     # the other reading of the ion-term extrapolation (to t^(k+1)), at the paper's time step

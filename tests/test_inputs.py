@@ -113,3 +113,18 @@ def test_table1_chi_cm_calibration():
         ev[nh] = e[-1] / e[0]
     assert abs(ev[512] - 1.34e4) <= 1e-3 * 1.34e4
     assert abs(ev[1024] - 2.89e4) <= 0.1 * 2.89e4
+
+
+def test_slab_mesh_has_a_plate_of_32_neighbours():
+    pr = problems.slab3d(n_grid=4, p=4, n_sub=3)
+    fe = np.asarray(pr.mesh.facet_elem)
+    nb = [set() for _ in range(pr.n_elem)]
+    for a, b in fe:
+        if a >= 0 and b >= 0:
+            nb[a].add(b)
+            nb[b].add(a)
+    deg = sorted(len(x) for x in nb)
+    assert pr.n_elem == 49 and deg[-1] == 32 and deg[-2] <= 6
+    # the plate is the only element of more than one cube (16 of them)
+    cubes = np.sort(np.diff(pr.mesh.cell_ptr))
+    assert cubes[-1] == 16 and cubes[-2] == 1
