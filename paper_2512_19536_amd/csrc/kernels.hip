@@ -662,10 +662,19 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     __syncthreads();
 }
 
+// Minimum waves per SIMD the register allocation must allow.  With FP32
+// local and coarse tiles the kernel takes 81 registers unconstrained (5
+// workgroups per CU); 80 (6 per CU) costs no spill and hides more of the
+// start-up latency of small items.  The BF16 form fits 6 already, and forms
+// with an FP64 path keep their allocation (a cap there spills).
+template <typename EL, typename EC> struct SchwarzMinWaves { static constexpr int value = 1; };
+template <> struct SchwarzMinWaves<float, float> { static constexpr int value = 6; };
+
 // One workgroup per item: a fresh workgroup hides the start-up latency of
 // the previous one on its CU (a persistent loop over items does not).
 template <typename EL, typename EC>
-__global__ __launch_bounds__(256) void k_schwarz(SchwarzArgs a, int max_nj) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SchwarzMinWaves<EL, EC>::value)))
+void k_schwarz(SchwarzArgs a, int max_nj) {
     const int item = blockIdx.x;
     if (a.mode != 0 && a.sc[a.item_owner[item]].done) return;
     extern __shared__ double smem[];

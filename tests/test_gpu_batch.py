@@ -143,7 +143,7 @@ def test_autotune_keeps_the_solution():
     i0 = ctx.solve(b, x0, 1e-10, 5000)
     res = ctx.autotune(reps=3)
     print(f"[autotune] {res}", flush=True)
-    assert res["item_kb"] in (64, 128, 256, 512, 1024) and res["spmv_waves"] in (1, 2, 4, 8)
+    assert res["item_kb"] in (64, 96, 128, 192, 256, 384, 512, 1024) and res["spmv_waves"] in (1, 2, 4, 8)
     assert res["schwarz_us"] > 0 and res["spmv_us"] > 0
     x1 = U.clone()
     i1 = ctx.solve(b, x1, 1e-10, 5000)
