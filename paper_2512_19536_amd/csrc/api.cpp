@@ -329,9 +329,12 @@ int store_kind(int prec) { return prec == PDG_F64 ? STORE_F64 : (prec == PDG_F32
 
 // Schwarz work items for a target of `kb` KiB of tiles per item: the stored
 // tiles (I, J <= I) of each packed tile row, split into even runs.  Order: per
-// batch system its subdomains (ascending), then its coarse system, so each
-// system's items (and tile rows) are one contiguous range.  With count_only
-// set, returns the item count and changes nothing.
+// batch system its coarse system, then its subdomains (ascending), so each
+// system's items (and tile rows) are one contiguous range.  Coarse items gather
+// their input from the restriction shares, which makes them slower to start;
+// launched first and split for a third of the size, they no longer form the
+// tail of the grid.  With count_only set, returns the item count and changes
+// nothing.
 int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
     const Precond &pc = c->pc;
     const int nd = c->mesh.nd;
@@ -351,7 +354,8 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
     auto add_sys = [&](int sidx, int b) {
         const int64_t nt = pc.sys[sidx].nt;
         const int prec = sidx < pc.n_sub ? pc.local_prec : pc.coarse_prec;
-        const int64_t jc = std::max<int64_t>(1, ((int64_t)kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
+        int64_t jc = std::max<int64_t>(1, ((int64_t)kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
+        if (sidx >= pc.n_sub) jc = std::max<int64_t>(1, jc / 3);
         for (int64_t I = 0; I < nt; ++I) {
             const int64_t ntile = I + 1, nc = (ntile + jc - 1) / jc;
             count += nc;
@@ -373,13 +377,13 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
         }
     };
     for (int b = 0; b < c->n_sys; ++b) {
-        for (int s : subs[b]) {
-            rt0_of_sub[s] = n_rt;
-            add_sys(s, b);
-        }
         if (pc.q > 0) {
             if (!count_only) c->coarse_rt0[b] = n_rt;
             add_sys(pc.n_sub + b, b);
+        }
+        for (int s : subs[b]) {
+            rt0_of_sub[s] = n_rt;
+            add_sys(s, b);
         }
         if (!count_only) c->r_itm[b + 1] = (int32_t)c->it_sys.size();
     }
