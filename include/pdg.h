@@ -195,7 +195,10 @@ pdg_status pdg_bind_workspace(pdg_ctx *ctx, void *dev_ptr, size_t bytes);
 typedef enum {
     PDG_OPT_TRUE_RESIDUAL = 1,  /* 1: pdg_solve/pdg_step compute ||b - Kx||/||b|| (one extra SpMV) */
     PDG_OPT_CHUNK = 2,          /* PCG iterations launched between host convergence polls (>= 1) */
-    PDG_OPT_KERNEL_TIMING = 3,  /* 1: time every Schwarz-apply launch with HIP events */
+    PDG_OPT_KERNEL_TIMING = 3,  /* k >= 1: time one in k Schwarz-apply launches of each solve
+                                   with HIP events stamped by the dispatch (1: every launch;
+                                   each timed launch adds a few microseconds to its PCG
+                                   iteration); 0 (default): off; above 2^20: PDG_EINVAL */
     PDG_OPT_SCHWARZ_ITEM_KB = 4,/* target tile bytes (KiB) per Schwarz work item, 32..8192,
                                    default 192; set before pdg_setup_preconditioner */
     PDG_OPT_GRAPH = 5,          /* 1: replay each chunk of PCG iterations as a captured HIP graph

@@ -136,6 +136,8 @@ struct pdg_ctx {
     // kernel timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     size_t ev_used = 0;
+    std::vector<int64_t> ev_idx;  // launch index (within the solve) of each used pool pair
+    int64_t t_seq = 0;            // Schwarz launches of the current solve so far
     int64_t t_launches = 0;
     double t_ms = 0.0;
 };
@@ -593,10 +595,12 @@ void launch_schwarz_plain(pdg_ctx *c, const SchwarzArgs &a, hipEvent_t e0 = null
                           c->max_nj, c->stream, e0, e1));
 }
 
-// With kernel timing on, the launch carries a pair of pool events that the
-// dispatch itself stamps at kernel start and end.
+// With kernel timing on, every `timing`-th Schwarz launch of a solve carries
+// a pair of pool events that the dispatch itself stamps at kernel start and
+// end (a timed launch costs the iteration a few microseconds more).
 void launch_schwarz_timed(pdg_ctx *c, const SchwarzArgs &a) {
-    if (!c->timing) {
+    const int64_t k = c->t_seq++;
+    if (!c->timing || k % c->timing != 0) {
         launch_schwarz_plain(c, a);
         return;
     }
@@ -605,22 +609,32 @@ void launch_schwarz_timed(pdg_ctx *c, const SchwarzArgs &a) {
         HIPCHK(hipEventCreate(&x));
         HIPCHK(hipEventCreate(&y));
         c->ev_pool.push_back({x, y});
+        c->ev_idx.push_back(0);
     }
+    c->ev_idx[c->ev_used] = k;
     launch_schwarz_plain(c, a, c->ev_pool[c->ev_used].first, c->ev_pool[c->ev_used].second);
     c->ev_used++;
 }
 
-// Collects the timings of the first `keep` recorded Schwarz launches of the
-// last solve (launches queued past convergence exit at once and are dropped).
-void harvest_timing(pdg_ctx *c, size_t keep) {
-    if (!c->timing) return;
-    for (size_t k = 0; k < c->ev_used && k < keep; ++k) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[k].first, c->ev_pool[k].second));
-        c->t_ms += ms;
-        c->t_launches++;
-    }
+// Starts the launch count of a solve (or of a single apply).
+void reset_timing_seq(pdg_ctx *c) {
     c->ev_used = 0;
+    c->t_seq = 0;
+}
+
+// Collects the timings of the recorded Schwarz launches among the first `keep`
+// launches of the last solve (launches queued past convergence exit at once
+// and are dropped).
+void harvest_timing(pdg_ctx *c, size_t keep) {
+    if (c->timing)
+        for (size_t k = 0; k < c->ev_used; ++k) {
+            if (c->ev_idx[k] >= (int64_t)keep) continue;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[k].first, c->ev_pool[k].second));
+            c->t_ms += ms;
+            c->t_launches++;
+        }
+    reset_timing_seq(c);
 }
 
 UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *sc) {
@@ -810,7 +824,7 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
         HIPCHK(launch_spmv(c->dA, a, s));
     }
     HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.x), vec(c, c->w.r), sc), s));
-    c->ev_used = 0;
+    reset_timing_seq(c);
     launch_precond(c, 1, sc, true);
     HIPCHK(launch_pupdate(pupdate_args(c, 1, vec(c, c->w.p), vec(c, c->w.r), sc), s));
     PcgRun &R = c->run;
@@ -1333,7 +1347,10 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             if (value < 1 || value > 1000) throw Error(PDG_EINVAL, "chunk must be in 1..1000");
             c->chunk = (int)value;
             break;
-        case PDG_OPT_KERNEL_TIMING: c->timing = value != 0; break;
+        case PDG_OPT_KERNEL_TIMING:
+            if (value < 0 || value > (1 << 20)) throw Error(PDG_EINVAL, "kernel timing period must be 0..2^20");
+            c->timing = (int)value;
+            break;
         case PDG_OPT_SCHWARZ_ITEM_KB:
             if (value < 32 || value > 8192) throw Error(PDG_EINVAL, "item size must be in 32..8192 KiB");
             if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "set the item size before pdg_setup_preconditioner");
@@ -1409,7 +1426,7 @@ pdg_status pdg_precond_apply(pdg_ctx *c, const double *r, double *z) {
         HIPCHK(launch_status_reset(sc, c->n_sys, -1.0, 0, 0, c->stream));
         // restriction only (init mode: x and r untouched)
         HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.t), const_cast<double *>(r), sc), c->stream));
-        c->ev_used = 0;
+        reset_timing_seq(c);
         if (!c->no_precond) launch_schwarz_timed(c, schwarz_args(c, 0, r, sc));
         HIPCHK(launch_pupdate(pupdate_args(c, 0, z, r, sc), c->stream));
         if (c->timing) {

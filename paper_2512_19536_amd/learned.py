@@ -252,7 +252,9 @@ def evaluate(mlp, problem, n_steps, device="cuda:0", options=None, extrapolate_o
     trajectory continues with the plain result."""
     torch = mlp.torch
     opts = dict(options or {})
-    opts[_lib.PDG_OPT_KERNEL_TIMING] = 1
+    # one Schwarz launch in eight timed: timing each launch would slow every
+    # iteration by a few microseconds in all three variants
+    opts[_lib.PDG_OPT_KERNEL_TIMING] = 8
     ctx = from_problem(problem, device=device, options=opts)
     U, Up, Y = initial_state(ctx, problem)
     n_elem, nd = problem.n_elem, problem.nd

@@ -115,11 +115,14 @@ def test_option_and_coarse_errors_from_the_host():
     ctx = solver.Context(None)
     for opt, val in ((_lib.PDG_OPT_PRECONDITIONER, 2), (_lib.PDG_OPT_LANCZOS_CAP, 0),
                      (_lib.PDG_OPT_LANCZOS_CAP, (1 << 20) + 1), (_lib.PDG_OPT_ION_EXTRAPOLATION, 2),
-                     (_lib.PDG_OPT_SCHWARZ_ITEM_KB, 16), (_lib.PDG_OPT_SPMV_WAVES, 3), (99, 1)):
+                     (_lib.PDG_OPT_SCHWARZ_ITEM_KB, 16), (_lib.PDG_OPT_SPMV_WAVES, 3),
+                     (_lib.PDG_OPT_KERNEL_TIMING, -1), (_lib.PDG_OPT_KERNEL_TIMING, (1 << 20) + 1), (99, 1)):
         _expect(_lib.PDG_EINVAL, ctx.set_option, opt, val)
-    for opt in (_lib.PDG_OPT_PRECONDITIONER, _lib.PDG_OPT_ION_EXTRAPOLATION):
+    for opt in (_lib.PDG_OPT_PRECONDITIONER, _lib.PDG_OPT_ION_EXTRAPOLATION, _lib.PDG_OPT_KERNEL_TIMING):
         ctx.set_option(opt, 0)
         ctx.set_option(opt, 1)
+    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 8)
+    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 0)
     ctx.set_mesh(pr.mesh, 2)
     ctx.assemble(1.0, 1.0, 0.05, 10.0)
     _expect(_lib.PDG_EINVAL, ctx.setup_preconditioner, pr.elem_sub, None, 3)  # q > p

@@ -145,6 +145,24 @@ def test_schwarz_apply(case):
     assert rel_max(N(z), md.schwarz.apply(r)) < 1e-11
 
 
+@pytest.mark.parametrize("period", [1, 3, 8])
+def test_kernel_timing_samples_the_launches_that_did_work(period):
+    """One Schwarz launch in `period` of a solve is timed: the init apply and
+    iterations 1..iters did work (launches queued past convergence do not
+    count), so ceil((iters + 1) / period) launches are reported."""
+    pr, md, ctx = _setup("3d_p2")
+    b = T(np.random.default_rng(5).standard_normal(pr.n_dof))
+    x = torch.zeros_like(b)
+    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, period)
+    ctx.kernel_timing()
+    info = ctx.solve(b, x, 1e-10, 5000)
+    n, ms, by = ctx.kernel_timing()
+    ctx.set_option(_lib.PDG_OPT_KERNEL_TIMING, 0)
+    assert info["iters"] > 2 * period
+    assert n == (info["iters"] + period) // period
+    assert ms > 0 and by > 0
+
+
 @pytest.mark.parametrize("case", ["cfg1", "2d_p4", "3d_p2", "3d_p4", "3d_p2_endpoint"])
 def test_project_ionic_rhs(case):
     pr, md, ctx = _setup(case)
