@@ -230,6 +230,14 @@ def slab3d(n_grid=4, p=4, n_sub=3, seed=21) -> Problem:
                                  None, 3.0, 1.0, 10.0, 0.05)
 
 
+def one_element3d(p=2) -> Problem:
+    """The degenerate 3-D case: a single element (2 x 2 x 2 cubes), one
+    subdomain and a coarse space on it; every facet is a boundary facet."""
+    mesh = cube_mesh_from_owner(np.zeros(8, dtype=np.int64), 2, 1.0, region_of_cube=np.zeros(8, dtype=np.int64))
+    return _problem_on_cube_mesh(f"one_element3d_p{p}", mesh, 1, 1, p, 0.0, "two_region", 3,
+                                 None, 3.0, 1.0, 10.0, 0.05)
+
+
 def small2d(n=24, p=2, seed=5) -> Problem:
     mesh = voronoi_mesh(n, seed=seed, lloyd=4)
     ne = mesh.n_elem

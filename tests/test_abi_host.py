@@ -1,5 +1,6 @@
 """C-ABI library on the host (no GPU): symbol exports, host-side setup parity
 against the oracle (independent implementations), and error codes."""
+import copy
 import os
 import re
 from dataclasses import replace
@@ -93,6 +94,12 @@ def test_error_codes_from_the_host():
     _expect(_lib.PDG_ESTATE, ctx.assemble, 1.0, 1.0, 0.05, 10.0)
     # bad degree
     _expect(_lib.PDG_EINVAL, ctx.set_mesh, pr.mesh, 7)
+    # empty mesh
+    empty = copy.deepcopy(pr.mesh)
+    empty.cell_ptr = np.zeros(1, np.int64)
+    for f in ("cell_geom", "facet_elem", "facet_geom", "facet_normal", "sigma"):
+        setattr(empty, f, getattr(pr.mesh, f)[:0])
+    _expect(_lib.PDG_EINVAL, ctx.set_mesh, empty, 2)
     ctx.set_mesh(pr.mesh, 2)
     _expect(_lib.PDG_EINVAL, ctx.assemble, 1.0, 1.0, -0.05, 10.0)
     ctx.assemble(1.0, 1.0, 0.05, 10.0)

@@ -60,6 +60,9 @@ CASES = {
     # a plate element with 32 neighbours: its matrix row spans three chunks
     # (16 + 16 + 1 blocks) of the layout for blocks of more than 32 rows
     "3d_p4_slab": lambda: problems.slab3d(n_grid=4, p=4, n_sub=3),
+    # one element: one subdomain of 10 dofs (one tile, mostly padding) and a
+    # 4-dof coarse system on it
+    "3d_one_element": lambda: problems.one_element3d(p=2),
     # subdomains of exactly 64 dofs (one full tile, no padding) and of 128 dofs
     "3d_p1_tile64": lambda: _blocks_of(problems.small3d(n_grid=8, p=1, n_sub=4), (16, 32)),
     # the other reading of the ion-term extrapolation (to t^(k+1)), at the paper's time step

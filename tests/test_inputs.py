@@ -128,3 +128,11 @@ def test_slab_mesh_has_a_plate_of_32_neighbours():
     # the plate is the only element of more than one cube (16 of them)
     cubes = np.sort(np.diff(pr.mesh.cell_ptr))
     assert cubes[-1] == 16 and cubes[-2] == 1
+
+
+def test_one_element_mesh_is_all_boundary():
+    pr = problems.one_element3d(p=2)
+    fe = np.asarray(pr.mesh.facet_elem)
+    assert pr.n_elem == 1 and pr.n_dof == 10 and len(fe) == 24
+    assert (fe[:, 0] == 0).all() and (fe[:, 1] == -1).all()
+    assert pr.elem_sub.tolist() == [0] and pr.coarse_q == 1
