@@ -200,7 +200,7 @@ typedef enum {
                                    each timed launch adds a few microseconds to its PCG
                                    iteration); 0 (default): off; above 2^20: PDG_EINVAL */
     PDG_OPT_SCHWARZ_ITEM_KB = 4,/* target tile bytes (KiB) per Schwarz work item, 32..8192,
-                                   default 192; set before pdg_setup_preconditioner */
+                                   default 128; set before pdg_setup_preconditioner */
     PDG_OPT_GRAPH = 5,          /* 1: replay each chunk of PCG iterations as a captured HIP graph
                                    (captured on first use; not while kernel timing is on);
                                    needs a non-NULL stream in pdg_create (else PDG_EINVAL) */

@@ -81,7 +81,7 @@ struct pdg_ctx {
     std::string err;
     int n_threads = 0;
     // options
-    int true_resid = 0, chunk = 4, timing = 0, item_kb = 192, use_graph = 0, spmv_wpg = 4;
+    int true_resid = 0, chunk = 4, timing = 0, item_kb = 128, use_graph = 0, spmv_wpg = 4;
     int prev_iters = 0;
     // host data
     Mesh mesh;

@@ -402,7 +402,7 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
 // one system; each tile is read once and used for both of its products
 // (see schwarz_item).  Each thread loads 16 bytes per tile row for RPT rows,
 // so every load instruction of a wavefront reads whole contiguous tile rows.
-// Items hold ~192 KiB of tiles by default, so the grid is many similar-sized
+// Items hold ~128 KiB of tiles by default, so the grid is many similar-sized
 // workgroups.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
