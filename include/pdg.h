@@ -200,7 +200,8 @@ typedef enum {
                                    each timed launch adds a few microseconds to its PCG
                                    iteration); 0 (default): off; above 2^20: PDG_EINVAL */
     PDG_OPT_SCHWARZ_ITEM_KB = 4,/* target tile bytes (KiB) per Schwarz work item, 32..8192,
-                                   default 128; set before pdg_setup_preconditioner */
+                                   default 128; items are cut further so that a workgroup's
+                                   LDS stays within 64 KiB; set before pdg_setup_preconditioner */
     PDG_OPT_GRAPH = 5,          /* 1: replay each chunk of PCG iterations as a captured HIP graph
                                    (captured on first use; not while kernel timing is on);
                                    needs a non-NULL stream in pdg_create (else PDG_EINVAL) */
@@ -212,10 +213,17 @@ typedef enum {
                                    pdg_lanczos, 1..2^20 (default 2048; 16 bytes each per
                                    system in the workspace).  Set before pdg_workspace_query /
                                    pdg_bind_workspace. */
-    PDG_OPT_ION_EXTRAPOLATION = 9 /* the potential in the explicit ion term of eq. (4):
-                                   0 (default): u~ = (3 u^k - u^(k-1)) / 2, extrapolated to the
-                                   Crank-Nicolson mid-point t^(k+1/2);
-                                   1: u~ = 2 u^k - u^(k-1), extrapolated to t^(k+1) */
+    PDG_OPT_ION_EXTRAPOLATION = 9,/* the potential in the explicit ion term of eq. (4):
+                                   1 (default): u~ = 2 u^k - u^(k-1), the second-order
+                                   extrapolation to t^(k+1) that eq. (4) writes as I^(k+1);
+                                   0: u~ = (3 u^k - u^(k-1)) / 2, extrapolated to the
+                                   Crank-Nicolson mid-point t^(k+1/2) (stable at larger time
+                                   steps, where the extrapolation to t^(k+1) can diverge) */
+    PDG_OPT_PRESUM = 10         /* 0 (default): a dedicated single-block reduction kernel
+                                   pre-sums the per-workgroup partials of (p, q), (r, z) and
+                                   (r, r) only where the consumers would otherwise read more
+                                   than 4M partials per system; 1: always.  Both paths add in
+                                   the same order (bitwise-equal results). */
 } pdg_option;
 pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 
@@ -258,7 +266,7 @@ pdg_status pdg_precond_apply(pdg_ctx *ctx, const double *r, double *z);
 
 /* Ionic update (second line of eq. (4)) and ion term: ions [5][n_elem][nd]
  * Y^k -> Y^(k+1) in place; I[e][i] = int_K f(u~, y^(k+1)) phi_i with the
- * extrapolated potential u~ = (3 u^k - u^(k-1)) / 2 (or 2 u^k - u^(k-1), see
+ * extrapolated potential u~ = 2 u^k - u^(k-1) (or (3 u^k - u^(k-1)) / 2, see
  * PDG_OPT_ION_EXTRAPOLATION).
  * Returns PDG_ENONFINITE (synchronising) if a concentration was <= 0. */
 pdg_status pdg_ionic(pdg_ctx *ctx, const double *u, const double *u_prev, double *ions,

@@ -17,7 +17,9 @@ Follows Section 3 of the paper:
 
 Pinned by: symmetry, A 1 = 0, positive definiteness (brute force on small
 meshes), consistency for global linear functions, polynomial reproduction and
-manufactured-solution convergence rates (tests/test_oracle_assembly.py).
+manufactured-solution convergence rates (tests/test_oracle_discretisation.py);
+the penalty of eq. (2) and the diameter h_K by the closed form of the SIPG form
+on indicator functions of hand-built elements (tests/test_oracle_penalty.py).
 """
 from __future__ import annotations
 

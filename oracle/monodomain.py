@@ -6,12 +6,12 @@ Per step k (Section 3):
    M Y_l^(k+1) = M Y_l^(k) - dt G_l^(k),  G_l,i = int_K m_l(u_h^k, y_h^k) phi_i,
    element by element (M is block diagonal);
 2. extrapolated ion term: I^(k+1)_i = int_K f(u~, y_h^(k+1)) phi_i with the
-   second-order explicit extrapolation of the potential to the Crank-Nicolson
-   mid-point, u~ = (3 u_h^k - u_h^(k-1)) / 2 (reading of the paper's
-   "second-order explicit extrapolation": the Adams-Bashforth-2 partner of the
-   Crank-Nicolson mid-point rule; the extrapolation to t^(k+1),
-   2 u^k - u^(k-1), is unstable at dt = 0.05 ms with this ionic model; it is
-   available as ``problem.ion_extrap = "endpoint"``);
+   second-order explicit extrapolation of the potential to t^(k+1),
+   u~ = 2 u_h^k - u_h^(k-1), as eq. (4) writes the term (default,
+   ``problem.ion_extrap = "endpoint"``).  The extrapolation to the
+   Crank-Nicolson mid-point, u~ = (3 u_h^k - u_h^(k-1)) / 2
+   (``"midpoint"``), is the reading taken at dt = 0.05 ms, where the
+   extrapolation to t^(k+1) diverges with this ionic model;
    at k = 0, U^(-1) := U^(0);
 3. right-hand side of the first line of eq. (4) divided by dt:
    b = (c M - 1/2 A) U^k - chi_m I + F = 2 c M U^k - K U^k - chi_m I + F,
@@ -40,8 +40,8 @@ class Monodomain:
         self.Mmat = d.mass_matrix()
         self.Minv = np.linalg.inv(d.M)
         self.prm = np.asarray(problem.ionic, dtype=np.float64)
-        # u~ of the ion term: (3u^k - u^(k-1))/2 at the mid-point, or 2u^k - u^(k-1) at t^(k+1)
-        mode = getattr(problem, "ion_extrap", "midpoint")
+        # u~ of the ion term: 2u^k - u^(k-1) at t^(k+1), or (3u^k - u^(k-1))/2 at the mid-point
+        mode = getattr(problem, "ion_extrap", "endpoint")
         self.ext = {"midpoint": (1.5, -0.5), "endpoint": (2.0, -1.0)}[mode]
         self.schwarz = None
         if with_schwarz:

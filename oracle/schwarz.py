@@ -53,8 +53,10 @@ class Schwarz:
             self.K0 = 0.5 * (self.K0 + self.K0.T)
             self.chol0 = sla.cho_factor(self.K0, lower=True)
 
-    def local_blocks(self):
-        """Dense K_i (for tests)."""
+    def local_factors(self):
+        """The scipy cho_factor storage of every K_i (for tests): its lower
+        triangle is the Cholesky factor L_i with L_i L_i^T = K_i; the entries
+        above the diagonal are left over from K_i and carry no meaning."""
         return [c[0] for c in self.chol]
 
     def apply(self, r):

@@ -111,7 +111,8 @@ struct pdg_ctx {
     int pre_rr = 0;              // same for (r, r) when no preconditioner is applied
     bool no_precond = false;     // B = I: plain CG
     int lcap = 2048;             // PCG coefficients kept per system (Lanczos estimate)
-    int ion_endpoint = 0;        // ion term at 2u^k - u^(k-1) instead of (3u^k - u^(k-1))/2
+    int ion_endpoint = 1;        // ion term at 2u^k - u^(k-1) (eq. (4)); 0: at (3u^k - u^(k-1))/2
+    int force_presum = 0;        // 1: the reduction kernel pre-sums the dot products at any size
     bool lanczos_ok = false;     // device scalars still hold the last solve
     // group-ELL matrix (host staging)
     int G = 1;
@@ -321,9 +322,9 @@ void choose_reductions(pdg_ctx *c) {
         pup = std::max(pup, n_pu * n_sw);
         pur = std::max(pur, n_pu * n_up);
     }
-    c->pre_pq = upd > kRedundantReads;
-    c->pre_rz = pup > kRedundantReads;
-    c->pre_rr = pur > kRedundantReads;
+    c->pre_pq = c->force_presum || upd > kRedundantReads;
+    c->pre_rz = c->force_presum || pup > kRedundantReads;
+    c->pre_rr = c->force_presum || pur > kRedundantReads;
 }
 
 size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32 ? 4 : 2); }
@@ -337,9 +338,22 @@ int store_kind(int prec) { return prec == PDG_F64 ? STORE_F64 : (prec == PDG_F32
 // launched first and split for a third of the size, they no longer form the
 // tail of the grid.  With count_only set, returns the item count and changes
 // nothing.
+// LDS one Schwarz workgroup may use; items are cut to fit it whatever the
+// requested size.
+constexpr size_t kSchwarzLdsMax = 65536;
+
+// Largest tile count per item whose LDS fits kSchwarzLdsMax.
+int64_t max_tiles_per_item(const pdg_ctx *c) {
+    const int ls = store_kind(c->pc.local_prec), cs = store_kind(c->pc.coarse_prec);
+    int64_t nj = 1;
+    while (schwarz_lds_bytes(ls, cs, (int)nj + 1) <= kSchwarzLdsMax) ++nj;
+    return nj;
+}
+
 int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
     const Precond &pc = c->pc;
     const int nd = c->mesh.nd;
+    const int64_t nj_cap = max_tiles_per_item(c);
     std::vector<std::vector<int>> subs(c->n_sys);
     for (int s = 0; s < pc.n_sub; ++s) subs[pc.sub_bsys[s]].push_back(s);
     int64_t count = 0;
@@ -358,6 +372,7 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
         const int prec = sidx < pc.n_sub ? pc.local_prec : pc.coarse_prec;
         int64_t jc = std::max<int64_t>(1, ((int64_t)kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
         if (sidx >= pc.n_sub) jc = std::max<int64_t>(1, jc / 3);
+        jc = std::min(jc, nj_cap);
         for (int64_t I = 0; I < nt; ++I) {
             const int64_t ntile = I + 1, nc = (ntile + jc - 1) / jc;
             count += nc;
@@ -1381,6 +1396,12 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             c->no_precond = value == 0;
             drop_graph(c);
             break;
+        case PDG_OPT_PRESUM:
+            if (value != 0 && value != 1) throw Error(PDG_EINVAL, "pre-summed reductions must be 0 (automatic) or 1 (always)");
+            c->force_presum = (int)value;
+            if (c->state >= S_PRECOND) choose_reductions(c);
+            drop_graph(c);
+            break;
         default: throw Error(PDG_EINVAL, "unknown option");
         }
     });
@@ -1650,8 +1671,6 @@ pdg_status pdg_autotune(pdg_ctx *c, int32_t reps, pdg_tune_result *out) {
             for (int kb : cand) {
                 if (plan_items(c, kb, true) > c->items_reserved) continue;
                 plan_items(c, kb, false);
-                if (schwarz_lds_bytes(store_kind(c->pc.local_prec), store_kind(c->pc.coarse_prec), c->max_nj) > 65536)
-                    continue;
                 upload_items(c);
                 const SchwarzArgs sa = schwarz_args(c, 0, r, sc);
                 double ms = 0.0;

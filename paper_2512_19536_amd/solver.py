@@ -234,8 +234,8 @@ def from_problem(problem, device="cuda:0", local_prec=None, coarse_prec=None, bi
     ctx = Context(device, stream)
     for k, v in (options or {}).items():
         ctx.set_option(k, v)
-    if getattr(problem, "ion_extrap", "midpoint") != "midpoint":
-        ctx.set_option(_lib.PDG_OPT_ION_EXTRAPOLATION, {"endpoint": 1}[problem.ion_extrap])
+    ctx.set_option(_lib.PDG_OPT_ION_EXTRAPOLATION,
+                   {"endpoint": 1, "midpoint": 0}[getattr(problem, "ion_extrap", "endpoint")])
     ctx.set_mesh(problem.mesh, problem.p)
     if getattr(problem, "elem_ptr", None) is not None:
         ctx.set_systems(problem.elem_ptr)

@@ -76,7 +76,11 @@ class Problem:
     coarse_prec: str = "f64"
     maxit: int = 5000
     elem_ptr: np.ndarray | None = None   # batch of independent systems: element range of each
-    ion_extrap: str = "midpoint"         # potential in the ion term: "midpoint" or "endpoint" (t^(k+1))
+    # potential in the explicit ion term of eq. (4): "endpoint" = 2u^k - u^(k-1)
+    # (extrapolated to t^(k+1), as the equation writes it) or "midpoint" =
+    # (3u^k - u^(k-1))/2; the workloads at dt = 0.05 ms take "midpoint", where
+    # the extrapolation to t^(k+1) diverges
+    ion_extrap: str = "endpoint"
 
     @property
     def n_elem(self):
@@ -143,7 +147,7 @@ def cfg1() -> Problem:
     u0[np.linalg.norm(cen, axis=1) < 0.1] += 30.0
     return Problem("cfg1", mesh, p=2, chi_m=1.0, c_m=1.0, dt=0.05, eta0=10.0,
                    elem_sub=sub.astype(np.int32), elem_coarse=sub.astype(np.int32), coarse_q=1,
-                   n_steps=10, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(n))
+                   n_steps=10, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(n), ion_extrap="midpoint")
 
 
 def _cube_problem(name, n_grid, length, seed_mesh, seed_part, n_sub, p, spread,
@@ -183,7 +187,8 @@ def _problem_on_cube_mesh(name, mesh, seed_part, n_sub, p, spread, sigma_kind, n
     u0[first] += 30.0
     return Problem(name, mesh, p=p, chi_m=1.0, c_m=1.0, dt=dt, eta0=10.0,
                    elem_sub=part.astype(np.int32), elem_coarse=part.astype(np.int32), coarse_q=1,
-                   n_steps=n_steps, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(n))
+                   n_steps=n_steps, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(n),
+                   ion_extrap="endpoint" if dt <= DT_3D else "midpoint")
 
 
 # 3-D workloads use the paper's time step (2.5 us).  With the explicit ion term
@@ -249,7 +254,7 @@ def small2d(n=24, p=2, seed=5) -> Problem:
     u0[np.linalg.norm(cen, axis=1) < 0.25] += 30.0
     return Problem(f"small2d_{n}_p{p}", mesh, p=p, chi_m=1.0, c_m=1.0, dt=0.05, eta0=10.0,
                    elem_sub=sub.astype(np.int32), elem_coarse=sub.astype(np.int32), coarse_q=1,
-                   n_steps=3, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(ne))
+                   n_steps=3, tol=1e-10, u0_elem=u0, y0_elem=_rest_state(ne), ion_extrap="midpoint")
 
 
 def trajectory_problem(base: Problem, seed, radius=None, white_ratio=3.0, prec="f32") -> Problem:
@@ -347,8 +352,8 @@ def concat_problems(name, probs) -> Problem:
     (meshes, labels and initial data concatenated; ``elem_ptr`` set)."""
     p0 = probs[0]
     for q in probs:
-        assert (q.p, q.dt, q.chi_m, q.c_m, q.eta0, q.coarse_q, q.tol, q.local_prec, q.coarse_prec) == \
-            (p0.p, p0.dt, p0.chi_m, p0.c_m, p0.eta0, p0.coarse_q, p0.tol, p0.local_prec, p0.coarse_prec)
+        assert (q.p, q.dt, q.chi_m, q.c_m, q.eta0, q.coarse_q, q.tol, q.local_prec, q.coarse_prec, q.ion_extrap) == \
+            (p0.p, p0.dt, p0.chi_m, p0.c_m, p0.eta0, p0.coarse_q, p0.tol, p0.local_prec, p0.coarse_prec, p0.ion_extrap)
         assert np.array_equal(q.ionic, p0.ionic)
     mesh, elem_ptr = concat_meshes([q.mesh for q in probs])
     sub_off = np.cumsum([0] + [int(q.elem_sub.max()) + 1 for q in probs])
@@ -360,7 +365,7 @@ def concat_problems(name, probs) -> Problem:
                    u0_elem=np.concatenate([q.u0_elem for q in probs]),
                    y0_elem=np.ascontiguousarray(np.concatenate([q.y0_elem for q in probs], axis=1)),
                    ionic=p0.ionic.copy(), local_prec=p0.local_prec, coarse_prec=p0.coarse_prec,
-                   maxit=p0.maxit, elem_ptr=elem_ptr)
+                   maxit=p0.maxit, elem_ptr=elem_ptr, ion_extrap=p0.ion_extrap)
 
 
 @dataclass

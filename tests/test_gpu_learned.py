@@ -236,3 +236,6 @@ def test_trained_network_lowers_iterations():
           f"guess used {np.mean(np.array(rec['used']) > 0):.2f}; max rel diff {max(rec['diff']):.1e}", flush=True)
     assert max(rec["diff"]) < 1e-8
     assert ml < mp
+    # and against the non-learned guess (linear extrapolation of the last two
+    # iterates, used wherever it lowers the initial residual)
+    assert ml < me

@@ -65,8 +65,12 @@ CASES = {
     "3d_one_element": lambda: problems.one_element3d(p=2),
     # subdomains of exactly 64 dofs (one full tile, no padding) and of 128 dofs
     "3d_p1_tile64": lambda: _blocks_of(problems.small3d(n_grid=8, p=1, n_sub=4), (16, 32)),
-    # the other reading of the ion-term extrapolation (to t^(k+1)), at the paper's time step
+    # both readings of the ion-term extrapolation at the paper's time step:
+    # to t^(k+1) (eq. (4), the default there) and to the mid-point
     "3d_p2_endpoint": lambda: replace(problems.small3d(n_grid=8, p=2, n_sub=6), dt=0.0025, ion_extrap="endpoint"),
+    "3d_p2_midpoint": lambda: replace(problems.small3d(n_grid=8, p=2, n_sub=6), dt=0.0025, ion_extrap="midpoint"),
+    # p = 1 at the paper's time step on the 3-D physics (k_ionic<3,1>)
+    "3d_p1_dt": lambda: problems.learned_small(n_grid=8, p=1, n_sub=6),
 }
 
 
@@ -166,7 +170,8 @@ def test_kernel_timing_samples_the_launches_that_did_work(period):
     assert ms > 0 and by > 0
 
 
-@pytest.mark.parametrize("case", ["cfg1", "2d_p4", "3d_p2", "3d_p4", "3d_p2_endpoint"])
+@pytest.mark.parametrize("case", ["cfg1", "2d_p1", "2d_p4", "3d_p1", "3d_p1_dt", "3d_p2", "3d_p4",
+                                  "3d_p2_endpoint", "3d_p2_midpoint", "t1_p1"])
 def test_project_ionic_rhs(case):
     pr, md, ctx = _setup(case)
     U0, _, Y0 = md.initial_state()
@@ -208,7 +213,8 @@ def test_solve(case):
     assert info["relres"] <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["cfg1", "3d_p2", "3d_p3", "t1_p3", "3d_p2_endpoint"])
+@pytest.mark.parametrize("case", ["cfg1", "2d_p1", "3d_p1", "3d_p1_dt", "3d_p2", "3d_p3", "t1_p1", "t1_p3",
+                                  "3d_p2_endpoint", "3d_p2_midpoint"])
 def test_time_steps(case):
     pr, md, ctx = _setup(case)
     nsteps = pr.n_steps if case == "cfg1" else 3
@@ -311,3 +317,89 @@ def test_unpreconditioned_cg(case):
     xp_after = T(x0)
     ctx.solve(T(b), xp_after, 1e-10, 2000)
     assert np.array_equal(N(xp_after), N(xp_before))
+
+
+# ---------------------------------------------------------------------------
+# The pre-summed dot products: a single-block reduction kernel sums the
+# per-workgroup partials of (p, q), (r, z) and (r, r) once (switched on by
+# itself only for systems of cfg3's size).  Forced on small systems, the solves
+# and time steps must match the oracle and be bitwise equal to the default path
+# (both sum in the same order).
+@pytest.mark.parametrize("case", ["cfg1", "3d_p2", "3d_p3", "t1_p1", "3d_p2_endpoint"])
+def test_presummed_reductions(case):
+    pr, md, ctx = _setup(case)
+    ctx_f = solver.from_problem(pr, device=DEV, options={_lib.PDG_OPT_PRESUM: 1})
+    rng = np.random.default_rng(41)
+    b = rng.standard_normal(pr.n_dof)
+    x0 = rng.standard_normal(pr.n_dof)
+    xo, oinfo = md.solve(b, x0, tol=1e-10)
+    xd, xf = T(x0), T(x0)
+    info_d = ctx.solve(T(b), xd, 1e-10, 2000)
+    info_f = ctx_f.solve(T(b), xf, 1e-10, 2000)
+    assert info_f["iters"] == info_d["iters"]
+    assert np.array_equal(N(xf), N(xd))
+    assert iters_agree(info_f["iters"], oinfo, 1e-10, np.linalg.norm(b))
+    assert rel_l2(N(xf), xo) < 1e-8
+    # plain CG (B = I) pre-sums (r, r) instead of (r, z)
+    ctx_f.set_option(_lib.PDG_OPT_PRECONDITIONER, 0)
+    ctx.set_option(_lib.PDG_OPT_PRECONDITIONER, 0)
+    try:
+        xd, xf = T(x0), T(x0)
+        info_d = ctx.solve(T(b), xd, 1e-10, 20000)
+        info_f = ctx_f.solve(T(b), xf, 1e-10, 20000)
+        assert info_f["iters"] == info_d["iters"] and np.array_equal(N(xf), N(xd))
+    finally:
+        ctx.set_option(_lib.PDG_OPT_PRECONDITIONER, 1)
+        ctx_f.set_option(_lib.PDG_OPT_PRECONDITIONER, 1)
+    # time steps
+    U, Up, Y = md.initial_state()
+    Ug, Upg, Yg = solver.initial_state(ctx_f, pr)
+    for k in range(2):
+        Yn_o, I_o = md.ionic_update(U, Up, Y)
+        b_o = md.rhs(U, I_o)
+        U, Up, Y, oinfo = md.step(U, Up, Y)
+        info = ctx_f.step(Ug, Upg, Yg, None, pr.tol, pr.maxit)
+        err = rel_l2(N(Ug), U)
+        print(f"{case} presum step {k}: iters gpu {info['iters']} oracle {oinfo.iters} relL2 {err:.2e}", flush=True)
+        assert iters_agree(info["iters"], oinfo, pr.tol, np.linalg.norm(b_o))
+        assert err < 1e-8
+    ctx_f.close()
+
+
+# ---------------------------------------------------------------------------
+# Device error statuses: each is detected on the device and returned by the call.
+def test_nan_rhs_gives_nonfinite():
+    pr, md, ctx = _setup("3d_p2")
+    b = np.random.default_rng(8).standard_normal(pr.n_dof)
+    b[pr.n_dof // 3] = np.nan
+    x = torch.zeros(pr.n_dof, dtype=torch.float64, device=DEV)
+    with pytest.raises(PdgError) as ei:
+        ctx.solve(T(b), x, 1e-10, 100)
+    assert ei.value.status == _lib.PDG_ENONFINITE
+    # the context still works afterwards
+    b[pr.n_dof // 3] = 1.0
+    info = ctx.solve(T(b), x, 1e-10, 1000)
+    assert info["relres"] <= 1e-10
+
+
+@pytest.mark.parametrize("call", ["ionic", "step"])
+def test_nonpositive_concentration_gives_nonfinite(call):
+    """A non-positive extracellular potassium [K]_o (ionic state 2) before its
+    logarithm is an error (the model is not evaluated there), not clamped."""
+    pr, md, ctx = _setup("3d_p2_endpoint")
+    U, Up, Y = md.initial_state()
+    Y = Y.reshape(5, pr.n_elem, pr.nd).copy()
+    e = pr.n_elem // 2
+    Y[2, e, :] = 0.0
+    Y[2, e, 0] = -1.0  # a negative constant on element e
+    Yd, Ud, Upd = T(Y.ravel()), T(U), T(Up)
+    with pytest.raises(PdgError) as ei:
+        if call == "ionic":
+            ctx.ionic(Ud, Upd, Yd, torch.empty(pr.n_dof, dtype=torch.float64, device=DEV))
+        else:
+            ctx.step(Ud, Upd, Yd, None, pr.tol, pr.maxit)
+    assert ei.value.status == _lib.PDG_ENONFINITE
+    # a valid state steps normally afterwards
+    U, Up, Y = md.initial_state()
+    info = ctx.step(T(U), T(Up), T(Y.ravel()), None, pr.tol, pr.maxit)
+    assert info["relres"] <= pr.tol

@@ -92,7 +92,7 @@ def test_schwarz_symmetric_positive_definite(small2d):
     assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
     # local part: restriction of K to each subdomain is the principal submatrix
     K = md.K.toarray()
-    for d, Ki in zip(md.schwarz.dofs, md.schwarz.local_blocks()):
+    for d, Ki in zip(md.schwarz.dofs, md.schwarz.local_factors()):
         L = np.tril(Ki)
         np.testing.assert_allclose(L @ L.T, K[np.ix_(d, d)], rtol=0, atol=1e-11 * abs(K).max())
 
