@@ -264,6 +264,22 @@ pdg_status pdg_spmv(pdg_ctx *ctx, const double *x, double *y);
 /* z = B^{-1} r (eq. (5)): all local solves plus the coarse correction. */
 pdg_status pdg_precond_apply(pdg_ctx *ctx, const double *r, double *z);
 
+/* pdg_precond_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same kernels and the same result, bit for bit, but the scratch of the
+ * apply (device scalars, coarse restriction shares, update partials, the
+ * Schwarz row and column partials) lives in a static device array of 64 MiB
+ * per device, set up by pdg_create and held until the process ends; the call
+ * itself allocates nothing and clears what it reads before writing it with
+ * kernels (no memset).  The scratch needs 512 bytes per stored inverse tile
+ * and per Schwarz work item plus small per-chunk terms; a context that needs
+ * more than 64 MiB gets PDG_EINVAL and should use pdg_precond_apply.  Every
+ * call on a device shares that device's array, which keeps the last call's
+ * contents: calls that overlap on one device (other streams, other
+ * contexts) race.  r, z: device, [n_elem][nd], caller-owned.  Call after
+ * pdg_bind_workspace; enqueue only (no synchronisation). */
+pdg_status pdg_precond_apply_noalloc(pdg_ctx *ctx, const double *r, double *z);
+
 /* Ionic update (second line of eq. (4)) and ion term: ions [5][n_elem][nd]
  * Y^k -> Y^(k+1) in place; I[e][i] = int_K f(u~, y^(k+1)) phi_i with the
  * extrapolated potential u~ = 2 u^k - u^(k-1) (or (3 u^k - u^(k-1)) / 2, see

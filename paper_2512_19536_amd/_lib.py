@@ -28,7 +28,7 @@ EXPORTS = (
     "pdg_get_sizes",
     "pdg_assemble", "pdg_get_matrix", "pdg_set_ionic", "pdg_setup_preconditioner", "pdg_get_precond_sizes",
     "pdg_get_local_inverse", "pdg_get_coarse", "pdg_workspace_query", "pdg_bind_workspace", "pdg_set_option",
-    "pdg_kernel_timing", "pdg_project_p0", "pdg_spmv", "pdg_precond_apply", "pdg_ionic", "pdg_rhs",
+    "pdg_kernel_timing", "pdg_project_p0", "pdg_spmv", "pdg_precond_apply", "pdg_precond_apply_noalloc", "pdg_ionic", "pdg_rhs",
     "pdg_solve", "pdg_step", "pdg_get_system_info", "pdg_step_batch", "pdg_autotune", "pdg_step_guess", "pdg_lanczos",
     "pdg_get_pcg_coefficients",
     "pdg_guess_extrapolate", "pdg_mlp_create", "pdg_mlp_destroy", "pdg_mlp_last_error", "pdg_mlp_get_sizes",
@@ -111,6 +111,7 @@ def load():
         "pdg_project_p0": (I32, [V, P, I32, P]),
         "pdg_spmv": (I32, [V, P, P]),
         "pdg_precond_apply": (I32, [V, P, P]),
+        "pdg_precond_apply_noalloc": (I32, [V, P, P]),
         "pdg_ionic": (I32, [V, P, P, P, P]),
         "pdg_rhs": (I32, [V, P, P, P, P]),
         "pdg_solve": (I32, [V, P, P, D, I32, POINTER(PdgSolveInfo)]),

@@ -1013,6 +1013,8 @@ pdg_status pdg_create(pdg_ctx **out, int32_t hip_device, void *hip_stream) {
             HIPCHK(hipGetDeviceCount(&n));
             if (hip_device >= n) throw Error(PDG_EINVAL, "no such HIP device");
             HIPCHK(hipSetDevice(hip_device));
+            // device address of the static scratch of pdg_precond_apply_noalloc
+            HIPCHK(static_scratch_init(hip_device));
         }
     });
     if (st != PDG_OK) {
@@ -1454,6 +1456,65 @@ pdg_status pdg_precond_apply(pdg_ctx *c, const double *r, double *z) {
             HIPCHK(hipStreamSynchronize(c->stream));
             harvest_timing(c, 1);
         }
+    });
+}
+
+pdg_status pdg_precond_apply_noalloc(pdg_ctx *c, const double *r, double *z) {
+    return guard(c, [&] {
+        require_gpu(c);
+        if (!r || !z) throw Error(PDG_EINVAL, "NULL vector");
+        char *base = static_cast<char *>(static_scratch(c->device));
+        if (!base) throw Error(PDG_ESTATE, "device scratch not set up");
+        // the scratch buffers of the apply (device scalars, restriction shares,
+        // update partials, Schwarz row and column partials), carved out of the
+        // device's static array
+        const Precond &pc = c->pc;
+        int64_t tiles = 0;
+        for (const DenseSys &S : pc.sys) tiles += S.nt * (S.nt + 1) / 2;
+        const int64_t n_chunks = (int64_t)c->grp_ptr.size() - 1, n_items = (int64_t)c->it_sys.size();
+        const size_t sz[6] = {c->n_sys * sizeof(DevScalars),
+                              (size_t)std::max<int64_t>(1, n_chunks * std::max(pc.nq0, 1)) * 8,
+                              (size_t)std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8,
+                              (size_t)n_items * kTile * 8,
+                              (size_t)tiles * kTile * 8,
+                              (size_t)std::max<int64_t>(1, n_items) * 8};
+        size_t off[6], total = 0;
+        for (int k = 0; k < 6; ++k) {
+            off[k] = total;
+            total = align256(total + sz[k]);
+        }
+        if (total > kStaticScratchBytes)
+            throw Error(PDG_EINVAL, "pdg_precond_apply_noalloc: this system needs " + std::to_string(total) +
+                                        " bytes of scratch, above the static limit of " +
+                                        std::to_string(kStaticScratchBytes) + " (use pdg_precond_apply)");
+        DevScalars *sc = reinterpret_cast<DevScalars *>(base + off[0]);
+        double *r0p = reinterpret_cast<double *>(base + off[1]);
+        double *rrp = reinterpret_cast<double *>(base + off[2]);
+        double *rowp = reinterpret_cast<double *>(base + off[3]);
+        double *colp = reinterpret_cast<double *>(base + off[4]);
+        double *itd = reinterpret_cast<double *>(base + off[5]);
+        hipStream_t s = c->stream;
+        // the scalars the kernels read are set by a kernel (no memset node
+        // if the caller captures this call in a graph)
+        HIPCHK(launch_status_reset(sc, c->n_sys, -1.0, 0, 0, s));
+        UpdateArgs u = update_args(c, 1, vec(c, c->w.t), const_cast<double *>(r), sc);
+        u.r0part = r0p;
+        u.rrpart = rrp;
+        HIPCHK(launch_update(u, s));
+        if (!c->no_precond) {
+            SchwarzArgs a = schwarz_args(c, 0, r, sc);
+            a.part = rowp;
+            a.colpart = colp;
+            a.itemdot = itd;
+            a.r0part = r0p;
+            launch_schwarz_plain(c, a);
+        }
+        PupdateArgs pu = pupdate_args(c, 0, z, r, sc);
+        pu.part = rowp;
+        pu.colpart = colp;
+        pu.itemdot = itd;
+        pu.rrpart = rrp;
+        HIPCHK(launch_pupdate(pu, s));
     });
 }
 

@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace pdg {
@@ -233,5 +234,13 @@ hipError_t launch_extrapolate(const double *u, const double *u1, const double *u
 // out = x on every dof, except 0 on the dofs of systems that stopped with a zero right-hand side.
 hipError_t launch_finish(const double *x, double *out, const int32_t *elem_sys, int nd, int64_t n_elem,
                          const DevScalars *sc, hipStream_t s);
+
+// Scratch of the allocation-free preconditioner apply: a static device array
+// of kStaticScratchBytes per device.  static_scratch_init looks up its address
+// on `device`, which must be the current device (once per device; later calls
+// return at once); static_scratch returns that address, or null before init.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+hipError_t static_scratch_init(int device);
+void *static_scratch(int device);
 
 }  // namespace pdg

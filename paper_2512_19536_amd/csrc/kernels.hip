@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -1512,6 +1513,42 @@ hipError_t launch_extrapolate(const double *u, const double *u1, const double *u
 hipError_t launch_status_reset(DevScalars *sc, int n_sys, double tol2, int maxit, int reset_ionic, hipStream_t s) {
     hipLaunchKernelGGL(k_status_reset, dim3(grid_for(n_sys)), dim3(256), 0, s, sc, n_sys, tol2, maxit, reset_ionic);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free preconditioner apply: one array per device,
+// held from the library's first use on that device until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory; every
+// host use goes through the address hipGetSymbolAddress returns for the
+// device that was current at set-up.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace pdg

@@ -162,6 +162,9 @@ class Context:
     def precond_apply(self, r, z):
         self._call("pdg_precond_apply", _ptr(r), _ptr(z))
 
+    def precond_apply_noalloc(self, r, z):
+        self._call("pdg_precond_apply_noalloc", _ptr(r), _ptr(z))
+
     def ionic(self, u, u_prev, ions, I):
         self._call("pdg_ionic", _ptr(u), _ptr(u_prev), _ptr(ions), _ptr(I))
 
