@@ -12,6 +12,10 @@
   2e-10; one system of each degree gives in its own context the same bits and
   iteration count; the two smallest systems agree with the FP64 oracle (which
   uses FP64 Schwarz solves) to 1e-8.
+* the long run of Section 5 (Fig. 2: p = q = 4, N_h = 4096, H = 4h, one
+  subdomain per element, 61,440 dofs and 3,840 coarse dofs): its first two
+  time steps against the oracle (equal iterations under the rule of
+  test_gpu_parity, relative L2 1e-8 on U and on the ionic state).
 """
 import numpy as np
 import pytest
@@ -142,3 +146,28 @@ def test_cfg4_batch_full_size():
         print(f"[cfg4] system {int(i)} vs oracle: iters gpu {bs.system_info(int(i))['iters']} "
               f"oracle {oinfo.iters}, rel L2 {err:.2e}", flush=True)
         assert err < 1e-8
+
+
+def test_fig2_long_run_configuration_against_oracle():
+    from oracle.monodomain import Monodomain
+    pr = problems.table1_problem(4096, 4, 4)
+    print(f"[fig2] {pr.name}: {pr.n_dof} dofs; oracle setup", flush=True)
+    md = Monodomain(pr)
+    ctx = solver.from_problem(pr, device=DEV)
+    U, Up, Y = md.initial_state()
+    Ug, Upg, Yg = solver.initial_state(ctx, pr)
+    for k in range(2):
+        Yn, I = md.ionic_update(U, Up, Y)
+        bnorm = np.linalg.norm(md.rhs(U, I))
+        U, Up, Y, oinfo = md.step(U, Up, Y)
+        info = ctx.step(Ug, Upg, Yg, None, pr.tol, pr.maxit)
+        err = rel_l2(N(Ug), U)
+        derr = rel_l2(N(Ug) - Up, U - Up)
+        print(f"[fig2] step {k}: iters gpu {info['iters']} oracle {oinfo.iters} rel L2 {err:.2e} "
+              f"(of the change {derr:.2e})", flush=True)
+        same = info["iters"] == oinfo.iters or (
+            abs(info["iters"] - oinfo.iters) == 1
+            and oinfo.resnorms[min(info["iters"], oinfo.iters)] <= 1.2 * pr.tol * bnorm)
+        assert same
+        assert err < 1e-8
+        assert rel_l2(N(Yg), Y.ravel()) < 1e-8
