@@ -718,7 +718,8 @@ def main():
     stream = ctx.stream
     for k in range(args.warmup):
         info = ctx.step(U, Up, Y, None, pr.tol, pr.maxit)
-        log(f"[bench] warmup step {k}: iters {info['iters']}")
+        log(f"[bench] warmup step {k}: iters {info['iters']}"
+            + (f", {info['local_fp32']} subdomains stored in FP32" if pr.local_prec == "bf16" else ""))
     # Schwarz kernel timed with HIP events inside the timed region; with graph
     # replay (no per-launch events possible) in two extra steps afterwards
     if not args.graph:

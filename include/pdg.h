@@ -65,6 +65,9 @@ typedef struct {
     double bnorm;         /* ||b||                                                 */
     int32_t guess_used;   /* pdg_step_guess: systems that started from the guess
                              (0 = all fell back to U^k); -1 = no guess offered      */
+    int32_t local_fp32;   /* BF16 local store: subdomains whose rounded inverse
+                             failed the positive-definiteness check at setup and
+                             are applied from FP32 tiles instead (0 otherwise)      */
 } pdg_solve_info;
 
 /* Create a context on HIP device `hip_device`, launching on `hip_stream`
@@ -154,7 +157,8 @@ pdg_status pdg_set_ionic(pdg_ctx *ctx, const double *params, int32_t n_params);
  * P^q on each coarse agglomerate (same modal basis on the agglomerate's
  * bounding box) and K_0 = P^T K P.  Local and coarse matrices are inverted
  * densely on the host in FP64 (Cholesky); the inverses are stored as packed
- * lower-triangular 64 x 64 tiles in `local_prec` / `coarse_prec`.
+ * lower-triangular 64 x 64 tiles in `local_prec` / `coarse_prec` (BF16 local
+ * tiles hold the inverse scaled to unit diagonal, see PDG_OPT_BF16_MARGIN).
  *   elem_sub    [n_elem] in 0..n_sub-1 (every subdomain non-empty)
  *   elem_coarse [n_elem] in 0..n_coarse-1, or NULL = the subdomains
  *   coarse_q    0 = one-level (no coarse correction), 1..p otherwise
@@ -219,11 +223,19 @@ typedef enum {
                                    0: u~ = (3 u^k - u^(k-1)) / 2, extrapolated to the
                                    Crank-Nicolson mid-point t^(k+1/2) (stable at larger time
                                    steps, where the extrapolation to t^(k+1) can diverge) */
-    PDG_OPT_PRESUM = 10         /* 0 (default): a dedicated single-block reduction kernel
+    PDG_OPT_PRESUM = 10,        /* 0 (default): a dedicated single-block reduction kernel
                                    pre-sums the per-workgroup partials of (p, q), (r, z) and
                                    (r, r) only where the consumers would otherwise read more
                                    than 4M partials per system; 1: always.  Both paths add in
                                    the same order (bitwise-equal results). */
+    PDG_OPT_BF16_MARGIN = 11    /* k in 0..40 (default 10), set before pdg_setup_preconditioner.
+                                   A BF16 local store keeps K_i^{-1} = D C D with
+                                   D = diag(K_i^{-1})^{1/2} in FP32 and C (unit diagonal) in
+                                   BF16, but only where the rounded C minus 2^-k I is positive
+                                   definite (checked on the host by Cholesky); elsewhere the
+                                   subdomain is stored in FP32 (counted in
+                                   pdg_solve_info.local_fp32).  k = 0 stores every subdomain
+                                   in FP32. */
 } pdg_option;
 pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 

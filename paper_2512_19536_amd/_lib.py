@@ -19,7 +19,7 @@ PDG_OK, PDG_EINVAL, PDG_ENOMEM, PDG_EHIP, PDG_ENOTSPD, PDG_ENOCONV, PDG_EBREAKDO
 PDG_F64, PDG_F32, PDG_BF16 = 0, 1, 2
 PDG_OPT_TRUE_RESIDUAL, PDG_OPT_CHUNK, PDG_OPT_KERNEL_TIMING, PDG_OPT_SCHWARZ_ITEM_KB = 1, 2, 3, 4
 PDG_OPT_GRAPH, PDG_OPT_SPMV_WAVES, PDG_OPT_PRECONDITIONER, PDG_OPT_LANCZOS_CAP = 5, 6, 7, 8
-PDG_OPT_ION_EXTRAPOLATION, PDG_OPT_PRESUM = 9, 10
+PDG_OPT_ION_EXTRAPOLATION, PDG_OPT_PRESUM, PDG_OPT_BF16_MARGIN = 9, 10, 11
 PRECISIONS = {"f64": PDG_F64, "f32": PDG_F32, "bf16": PDG_BF16}
 
 #: every symbol declared in include/pdg.h
@@ -51,11 +51,11 @@ class PdgPrecondDesc(ctypes.Structure):
 
 class PdgSolveInfo(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("relres", c_double), ("true_relres", c_double), ("bnorm", c_double),
-                ("guess_used", c_int32)]
+                ("guess_used", c_int32), ("local_fp32", c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "relres": self.relres, "true_relres": self.true_relres, "bnorm": self.bnorm,
-                "guess_used": self.guess_used}
+                "guess_used": self.guess_used, "local_fp32": self.local_fp32}
 
 
 class PdgMlpDesc(ctypes.Structure):

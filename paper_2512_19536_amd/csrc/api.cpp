@@ -28,15 +28,6 @@ enum State { S_CREATED = 0, S_MESH = 1, S_ASSEMBLED = 2, S_PRECOND = 3, S_BOUND 
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-uint16_t to_bf16(double v) {
-    float f = (float)v;
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf/nan
-    u += 0x7fffu + ((u >> 16) & 1u);                                     // round to nearest even
-    return (uint16_t)(u >> 16);
-}
-
 struct Layout {
     struct Item { size_t off = 0, bytes = 0; };
     std::vector<Item> items;
@@ -59,6 +50,7 @@ struct Ws {
     int grpptr, grpel, upsys, cchunk, csys0, rspmv, rupd, ritem, rowner;
     int spwg, upwg, chunk0, lanc, pucr, cbase;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
+    int tfb, dsc, rbase, sysf32;  // BF16 local store: FP32 fallback tiles, scales, their offsets, flags
 };
 
 // State of the PCG run in progress (between pcg_begin and pcg_end).
@@ -113,6 +105,8 @@ struct pdg_ctx {
     int lcap = 2048;             // PCG coefficients kept per system (Lanczos estimate)
     int ion_endpoint = 1;        // ion term at 2u^k - u^(k-1) (eq. (4)); 0: at (3u^k - u^(k-1))/2
     int force_presum = 0;        // 1: the reduction kernel pre-sums the dot products at any size
+    int bf16_margin_log2 = 10;   // BF16 local store: the rounded scaled inverse must keep
+                                 // its eigenvalues above 2^-bf16_margin_log2
     bool lanczos_ok = false;     // device scalars still hold the last solve
     // group-ELL matrix (host staging)
     int G = 1;
@@ -330,6 +324,14 @@ void choose_reductions(pdg_ctx *c) {
 size_t tile_elem_bytes(int prec) { return prec == PDG_F64 ? 8 : (prec == PDG_F32 ? 4 : 2); }
 int store_kind(int prec) { return prec == PDG_F64 ? STORE_F64 : (prec == PDG_F32 ? STORE_F32 : STORE_BF16); }
 
+// Storage precision of dense system sidx (local systems of a BF16 store that
+// failed the positive-definiteness check of their rounded form are FP32).
+int sys_prec(const Precond &pc, size_t sidx) {
+    if ((int)sidx >= pc.n_sub) return pc.coarse_prec;
+    if (pc.local_prec == PDG_BF16 && pc.fallback[sidx]) return PDG_F32;
+    return pc.local_prec;
+}
+
 // Schwarz work items for a target of `kb` KiB of tiles per item: the stored
 // tiles (I, J <= I) of each packed tile row, split into even runs.  Order: per
 // batch system its coarse system, then its subdomains (ascending), so each
@@ -369,7 +371,7 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
     int32_t n_rt = 0;
     auto add_sys = [&](int sidx, int b) {
         const int64_t nt = pc.sys[sidx].nt;
-        const int prec = sidx < pc.n_sub ? pc.local_prec : pc.coarse_prec;
+        const int prec = sys_prec(pc, sidx);
         int64_t jc = std::max<int64_t>(1, ((int64_t)kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
         if (sidx >= pc.n_sub) jc = std::max<int64_t>(1, jc / 3);
         jc = std::min(jc, nj_cap);
@@ -464,6 +466,14 @@ void plan_layout(pdg_ctx *c) {
     w.colp = L.add((local_tiles + coarse_tiles) * kTile * 8);
     w.tloc = L.add(local_tiles * kTile * kTile * tile_elem_bytes(pc.local_prec));
     w.tcoa = L.add(coarse_tiles * kTile * kTile * tile_elem_bytes(pc.coarse_prec));
+    int64_t fb_tiles = 0;
+    if (pc.local_prec == PDG_BF16)
+        for (int s = 0; s < pc.n_sub; ++s)
+            if (pc.fallback[s]) fb_tiles += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
+    w.tfb = L.add(fb_tiles * kTile * kTile * 4);
+    w.dsc = L.add(pc.dscale.size() * 4);
+    w.rbase = L.add(n_dsys * 8);
+    w.sysf32 = L.add(n_dsys * 4);
     w.P = L.add(pc.P.size() * 8);
     w.ecoa = L.add(pc.elem_coarse.size() * 4);
     w.elsys = L.add(n * 4);
@@ -602,6 +612,12 @@ SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) 
     a.r = r;
     a.r0part = wptr<double>(c, c->w.r0p);
     a.sc = sc;
+    if (c->pc.local_prec == PDG_BF16) {
+        a.dscale = wptr<float>(c, c->w.dsc);
+        a.sys_rbase = wptr<int64_t>(c, c->w.rbase);
+        a.sys_f32 = wptr<int32_t>(c, c->w.sysf32);
+        a.tiles_fallback = wptr<char>(c, c->w.tfb);
+    }
     return a;
 }
 
@@ -914,6 +930,7 @@ pdg_status pcg_end(pdg_ctx *c, pdg_solve_info *info, int *bad_sys) {
     }
     pdg_solve_info out{};
     out.guess_used = -1;
+    out.local_fp32 = c->pc.n_fallback;
     for (const DevScalars &h : c->last)
         if (h.guess >= 0) out.guess_used = std::max(out.guess_used, 0) + h.guess;
     double bb = 0.0;
@@ -1136,7 +1153,8 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
     return guard(c, [&] {
         require(c, S_ASSEMBLED, "pdg_setup_preconditioner");
         if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "preconditioner already set up");
-        setup_precond(c->mesh, c->K, c->M, d, c->elem_sys, c->n_sys, c->pc, c->n_threads);
+        setup_precond(c->mesh, c->K, c->M, d, c->elem_sys, c->n_sys, c->pc, c->n_threads,
+                      std::ldexp(1.0, -c->bf16_margin_log2));
         build_group_ell(c);
         plan_chunks(c);
         plan_items(c, c->item_kb, false);
@@ -1151,7 +1169,7 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         int64_t tile_bytes = 0;
         for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx) {
             const DenseSys &S = c->pc.sys[sidx];
-            const int64_t es = (int64_t)tile_elem_bytes((int)sidx < c->pc.n_sub ? c->pc.local_prec : c->pc.coarse_prec);
+            const int64_t es = (int64_t)tile_elem_bytes(sys_prec(c->pc, sidx));
             const int cw = (int)(16 / es);
             for (int64_t I = 0; I < S.nt; ++I) {
                 const int rows = (int)std::min<int64_t>(kTile, S.n - I * kTile);
@@ -1162,6 +1180,7 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         }
         const int64_t N = c->mesh.n_elem * c->mesh.nd;
         c->schwarz_bytes = tile_bytes + 3 * N * 8 + 3 * std::max<int64_t>(c->pc.N0, 0) * 8;
+        if (c->pc.local_prec == PDG_BF16) c->schwarz_bytes += N * 4;  // the FP32 scales
         c->state = S_PRECOND;
     });
 }
@@ -1277,13 +1296,32 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         std::vector<int64_t> sys_toff, sys_cb;
         int64_t nloc_tiles = 0;
         for (int sidx = 0; sidx < pc.n_sub; ++sidx) nloc_tiles += pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2;
+        // BF16 local store: FP32 fallback systems get offsets in the fallback store
+        const bool loc_b16 = pc.local_prec == PDG_BF16;
+        std::vector<int64_t> fb_off(pc.sys.size(), -1), rbase(pc.sys.size(), 0);
+        std::vector<int32_t> sys_f32(pc.sys.size(), 0);
+        int64_t fb_tiles = 0;
+        if (loc_b16)
+            for (int sidx = 0; sidx < pc.n_sub; ++sidx) {
+                rbase[sidx] = pc.rbase[sidx];
+                if (!pc.fallback[sidx]) continue;
+                sys_f32[sidx] = 1;
+                fb_off[sidx] = fb_tiles;
+                fb_tiles += pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2;
+            }
         for (size_t sidx = 0; sidx < pc.sys.size(); ++sidx) {
             sys_n.push_back((int32_t)pc.sys[sidx].n);
             sys_nt.push_back((int32_t)pc.sys[sidx].nt);
-            // local systems index the local store, coarse systems the coarse store
-            sys_toff.push_back((int)sidx < pc.n_sub ? pc.sys[sidx].tile_off : pc.sys[sidx].tile_off - nloc_tiles);
+            // local systems index the local store (or the fallback store),
+            // coarse systems the coarse store
+            sys_toff.push_back(fb_off[sidx] >= 0 ? fb_off[sidx]
+                               : (int)sidx < pc.n_sub ? pc.sys[sidx].tile_off
+                                                      : pc.sys[sidx].tile_off - nloc_tiles);
             sys_cb.push_back(pc.sys[sidx].tile_off);
         }
+        upload(c, w.rbase, rbase);
+        upload(c, w.sysf32, sys_f32);
+        if (loc_b16) upload(c, w.dsc, pc.dscale);
         upload(c, w.sysn, sys_n);
         upload(c, w.sysnt, sys_nt);
         upload(c, w.systoff, sys_toff);
@@ -1313,12 +1351,30 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
                 HIPCHK(hipStreamSynchronize(c->stream));
             } else {
                 b16.resize(count);
-                for (int64_t k = 0; k < count; ++k) b16[k] = to_bf16(src[k]);
+                for (int64_t k = 0; k < count; ++k) b16[k] = bf16_bits(src[k]);
                 HIPCHK(hipMemcpyAsync(c->ws + c->lay.items[item].off, b16.data(), count * 2, hipMemcpyHostToDevice, c->stream));
                 HIPCHK(hipStreamSynchronize(c->stream));
             }
         };
-        put_tiles(w.tloc, pc.inv64.data(), nloc, pc.local_prec);
+        if (loc_b16) {
+            // scaled BF16 tiles formed at setup; FP32 tiles of the fallback systems
+            if (nloc > 0)
+                HIPCHK(hipMemcpyAsync(c->ws + c->lay.items[w.tloc].off, pc.tiles_b16.data(), nloc * 2,
+                                      hipMemcpyHostToDevice, c->stream));
+            for (int sidx = 0; sidx < pc.n_sub; ++sidx) {
+                if (!pc.fallback[sidx]) continue;
+                const int64_t cnt = pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2 * kTile * kTile;
+                f32.resize(cnt);
+                const double *src = pc.inv64.data() + pc.sys[sidx].tile_off * kTile * kTile;
+                for (int64_t k = 0; k < cnt; ++k) f32[k] = (float)src[k];
+                HIPCHK(hipMemcpyAsync(c->ws + c->lay.items[w.tfb].off + fb_off[sidx] * kTile * kTile * 4, f32.data(),
+                                      cnt * 4, hipMemcpyHostToDevice, c->stream));
+                HIPCHK(hipStreamSynchronize(c->stream));
+            }
+            HIPCHK(hipStreamSynchronize(c->stream));
+        } else {
+            put_tiles(w.tloc, pc.inv64.data(), nloc, pc.local_prec);
+        }
         put_tiles(w.tcoa, pc.inv64.data() + nloc, ncoa, pc.coarse_prec);
         upload(c, w.P, pc.P);
         upload(c, w.ecoa, pc.elem_coarse);
@@ -1397,6 +1453,11 @@ pdg_status pdg_set_option(pdg_ctx *c, int32_t option, int64_t value) {
             if (value != 0 && value != 1) throw Error(PDG_EINVAL, "preconditioner must be 0 (none) or 1 (Schwarz)");
             c->no_precond = value == 0;
             drop_graph(c);
+            break;
+        case PDG_OPT_BF16_MARGIN:
+            if (value < 0 || value > 40) throw Error(PDG_EINVAL, "BF16 margin exponent must be in 0..40");
+            if (c->state >= S_PRECOND) throw Error(PDG_ESTATE, "set the BF16 margin before pdg_setup_preconditioner");
+            c->bf16_margin_log2 = (int)value;
             break;
         case PDG_OPT_PRESUM:
             if (value != 0 && value != 1) throw Error(PDG_EINVAL, "pre-summed reductions must be 0 (automatic) or 1 (always)");
@@ -1658,6 +1719,9 @@ pdg_status pdg_get_system_info(const pdg_ctx *cc, int32_t sys, pdg_solve_info *i
             info->bnorm = std::sqrt(h.bb);
             info->relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
             info->true_relres = c->last_true[sys];
+            info->local_fp32 = 0;
+            for (int s = 0; s < c->pc.n_sub && !c->pc.fallback.empty(); ++s)
+                if (c->pc.sub_bsys[s] == sys) info->local_fp32 += c->pc.fallback[s];
         }
         if (status) *status = map_status(h.status == ST_RUN ? ST_NOCONV : h.status);
     });

@@ -133,6 +133,14 @@ struct SchwarzArgs {
     const double *r;        // fine residual
     const double *r0part;   // per-chunk coarse restriction (summed on gather)
     DevScalars *sc;
+    // BF16 local store only (else null): the stored tiles of local system s
+    // hold C = D^{-1} K_s^{-1} D^{-1}; d of its row i is dscale[sys_rbase[s] + i].
+    // Systems with sys_f32[s] = 1 are stored in FP32 in tiles_fallback instead
+    // (sys_toff then indexes that store), unscaled.
+    const float *dscale;
+    const int64_t *sys_rbase;
+    const int32_t *sys_f32;
+    const void *tiles_fallback;
 };
 
 // Assembles z = B r from the Schwarz partials (row partials of the items of

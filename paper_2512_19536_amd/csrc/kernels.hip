@@ -24,6 +24,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -544,19 +545,23 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         load(bA, j0);
         load(bB, j0 + 1);
     }
+    // BF16 tiles hold the scaled inverse C = D^{-1} K^{-1} D^{-1}: the products
+    // run on D x and their results are scaled by D (rows past n have d = 0)
+    constexpr bool kScaled = std::is_same<E, uint16_t>::value;
+    const float *ds = kScaled ? a.dscale + a.sys_rbase[s] : nullptr;
     // gather x over the item's tile columns and over tile row I
     const int base = j0 * TILE;
     for (int t = tid; t < nj * TILE; t += 256) {
         const int gi = base + t;
         const double v = gi < n ? sys_input(a, s, coarse, dof0, gi) : 0.0;
         x64[t] = v;
-        if (sizeof(A) != 8) xa[t] = (A)v;
+        if (sizeof(A) != 8) xa[t] = (A)(kScaled ? v * (double)ds[gi] : v);
     }
     if (tid < TILE) {
         const int gi = I * TILE + tid;
         const double v = gi < n ? sys_input(a, s, coarse, dof0, gi) : 0.0;
         xI64[tid] = v;
-        if (sizeof(A) != 8) xIa[tid] = (A)v;
+        if (sizeof(A) != 8) xIa[tid] = (A)(kScaled ? v * (double)ds[gi] : v);
         *r_own = v;
     }
     __syncthreads();
@@ -638,8 +643,9 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     if (tid < TILE)
         for (int jj2 = 0; jj2 < nj; ++jj2) {
             const A *cx = colx + jj2 * 4 * TILE;
-            const double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
-                             (double)cx[3 * TILE + tid];
+            double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
+                       (double)cx[3 * TILE + tid];
+            if (kScaled && j0 + jj2 < I) v *= (double)ds[(j0 + jj2) * TILE + tid];
             if (j0 + jj2 < I) {
                 a.colpart[(cbase + j0 + jj2) * TILE + tid] = v;
                 dcol = fma(x64[jj2 * TILE + tid], v, dcol);
@@ -658,7 +664,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         A y = 0;
         const int arg = ar / RPT, ak = ar % RPT;
         for (int c = 0; c < NC; ++c) y += sR[(arg * NC + c) * RPT + ak];
-        yout[ar] = (double)y + diag_add;
+        yout[ar] = kScaled ? ((double)y + diag_add) * (double)ds[I * TILE + ar] : (double)y + diag_add;
     }
     __syncthreads();
 }
@@ -684,12 +690,24 @@ void k_schwarz(SchwarzArgs a, int max_nj) {
     const int s = a.item_sys[item], I = a.item_row[item], j0 = a.item_j0[item], nj = a.item_nj[item];
     const bool coarse = s >= a.n_sub;
     double r_own = 0.0, dcol = 0.0;
-    if (!coarse)
-        schwarz_item<EL>(a, reinterpret_cast<const EL *>(a.tiles_local), s, I, j0, nj, false, smem, max_nj, yout,
-                         &r_own, &dcol);
-    else
-        schwarz_item<EC>(a, reinterpret_cast<const EC *>(a.tiles_coarse), s, I, j0, nj, true, smem, max_nj, yout,
-                         &r_own, &dcol);
+    const EL *tl = reinterpret_cast<const EL *>(a.tiles_local);
+    const EC *tc = reinterpret_cast<const EC *>(a.tiles_coarse);
+    if constexpr (std::is_same<EL, uint16_t>::value) {
+        // BF16 local store: systems whose rounded inverse failed the
+        // positive-definiteness check are stored in FP32
+        if (!coarse && a.sys_f32[s])
+            schwarz_item<float>(a, reinterpret_cast<const float *>(a.tiles_fallback), s, I, j0, nj, false, smem,
+                                max_nj, yout, &r_own, &dcol);
+        else if (!coarse)
+            schwarz_item<EL>(a, tl, s, I, j0, nj, false, smem, max_nj, yout, &r_own, &dcol);
+        else
+            schwarz_item<EC>(a, tc, s, I, j0, nj, true, smem, max_nj, yout, &r_own, &dcol);
+    } else {
+        if (!coarse)
+            schwarz_item<EL>(a, tl, s, I, j0, nj, false, smem, max_nj, yout, &r_own, &dcol);
+        else
+            schwarz_item<EC>(a, tc, s, I, j0, nj, true, smem, max_nj, yout, &r_own, &dcol);
+    }
     if (tid < TILE) {
         const double y = yout[tid];
         a.part[(int64_t)item * TILE + tid] = y;
@@ -1381,8 +1399,12 @@ static size_t lds_need(size_t acc, size_t scratch, int max_nj) {
 
 template <typename EL, typename EC>
 static size_t schwarz_bytes_t(int max_nj) {
-    const size_t bl = lds_need(acc_size<EL>(), scratch_bytes<EL>(), max_nj);
+    size_t bl = lds_need(acc_size<EL>(), scratch_bytes<EL>(), max_nj);
     const size_t bc = lds_need(acc_size<EC>(), scratch_bytes<EC>(), max_nj);
+    if (std::is_same<EL, uint16_t>::value) {  // FP32-stored fallback systems
+        const size_t bf = lds_need(acc_size<float>(), scratch_bytes<float>(), max_nj);
+        bl = bl > bf ? bl : bf;
+    }
     return bl > bc ? bl : bc;
 }
 

@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -69,6 +70,22 @@ struct DenseSys {
     int64_t tile_off = 0;   // offset (in tiles) into the tile store
 };
 
+// bfloat16 of v: v rounded to FP32, then to 8 significant bits (nearest, ties to even).
+inline uint16_t bf16_bits(double v) {
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+inline double bf16_value(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
 struct Precond {
     int n_sub = 0, n_coarse = 0, q = 0, nq0 = 0;
     int n_bsys = 1;                                // independent systems of the batch
@@ -82,6 +99,14 @@ struct Precond {
     std::vector<int32_t> elem_coarse;              // internal coarse element of each element
     std::vector<DenseSys> sys;                     // n_sub local systems, then one coarse system per batch system
     std::vector<double> inv64;                     // FP64 inverse tiles (all systems)
+    // BF16 local store: K_i^{-1} = D_i C_i D_i with D_i = diag(K_i^{-1})^{1/2}
+    // (kept in FP32) and C_i (unit diagonal) rounded to BF16.  A C_i whose
+    // rounded form fails the positive-definiteness check is stored in FP32.
+    std::vector<uint16_t> tiles_b16;               // C_i tiles of the local systems (local tile offsets)
+    std::vector<float> dscale;                     // d of every local system, nt * 64 rows each (0 past n)
+    std::vector<int64_t> rbase;                    // [n_sub] first row of each local system in dscale
+    std::vector<int32_t> fallback;                 // [n_sub] 1: stored in FP32
+    int n_fallback = 0;
     int64_t n_tiles = 0;
     std::vector<double> P;                         // [n_elem][nd][nq0]
     std::vector<std::vector<double>> K0blk;        // K0 of each batch system, internal order
@@ -89,9 +114,11 @@ struct Precond {
 };
 
 // elem_bsys: batch system of every element (all 0 for one system).
+// bf16_margin: a BF16 local store keeps C_i only if C_i rounded to BF16,
+// minus bf16_margin times the identity, is positive definite.
 void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
                    const pdg_precond_desc *d, const std::vector<int32_t> &elem_bsys, int n_bsys, Precond &pc,
-                   int n_threads);
+                   int n_threads, double bf16_margin);
 void dense_inverse_of_system(const Precond &pc, int s, std::vector<double> &out);
 
 }  // namespace pdg

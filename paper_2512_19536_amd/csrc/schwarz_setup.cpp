@@ -118,6 +118,48 @@ void spd_inverse(int64_t n, double *A, int n_threads) {
     }
 }
 
+// Cholesky factorisation of the SPD matrix A (row-major n x n) in its lower
+// triangle, in place; false at the first pivot that is not positive.
+static bool cholesky_in_place(int64_t n, double *A) {
+    for (int64_t j = 0; j < n; ++j) {
+        double *Aj = &A[j * n];
+        const double s = Aj[j] - dot(Aj, Aj, j);
+        if (!(s > 0.0) || !std::isfinite(s)) return false;
+        Aj[j] = std::sqrt(s);
+        for (int64_t i = j + 1; i < n; ++i) {
+            double *Ai = &A[i * n];
+            Ai[j] = (Ai[j] - dot(Ai, Aj, j)) / Aj[j];
+        }
+    }
+    return true;
+}
+
+// BF16 form of the inverse D (row-major n x n, SPD) of a local system:
+// d_j = sqrt(D_jj) (rounded to FP32) into ds, the packed tiles of
+// C = diag(d)^{-1} D diag(d)^{-1} rounded to BF16 into tiles; true if the
+// rounded C minus margin * I is positive definite.  Overwrites D.
+static bool bf16_scaled_tiles(double *D, int64_t n, double margin, float *ds, uint16_t *tiles) {
+    for (int64_t j = 0; j < n; ++j) ds[j] = (float)std::sqrt(D[j * n + j]);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            const double v = bf16_value(bf16_bits(D[i * n + j] / ((double)ds[i] * (double)ds[j])));
+            D[i * n + j] = v;
+            D[j * n + i] = v;
+        }
+    const int64_t nt = (n + kTile - 1) / kTile;
+    for (int64_t I = 0; I < nt; ++I)
+        for (int64_t J = 0; J <= I; ++J) {
+            uint16_t *t = tiles + (I * (I + 1) / 2 + J) * kTile * kTile;
+            for (int r = 0; r < kTile; ++r)
+                for (int c = 0; c < kTile; ++c) {
+                    const int64_t gr = I * kTile + r, gc = J * kTile + c;
+                    t[r * kTile + c] = (gr < n && gc < n) ? bf16_bits(D[gr * n + gc]) : (uint16_t)0;
+                }
+        }
+    for (int64_t j = 0; j < n; ++j) D[j * n + j] -= margin;
+    return cholesky_in_place(n, D);
+}
+
 static void store_tiles(const double *D, int64_t n, double *tiles) {
     const int64_t nt = (n + kTile - 1) / kTile;
     for (int64_t I = 0; I < nt; ++I)
@@ -150,7 +192,7 @@ void dense_inverse_of_system(const Precond &pc, int s, std::vector<double> &out)
 
 void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
                    const pdg_precond_desc *d, const std::vector<int32_t> &elem_bsys, int n_bsys, Precond &pc,
-                   int n_threads) {
+                   int n_threads, double bf16_margin) {
     if (!d || d->n_sub < 1 || !d->elem_sub) throw Error(PDG_EINVAL, "bad preconditioner descriptor");
     const int64_t n = m.n_elem;
     const int nd = m.nd, dim = m.dim;
@@ -334,6 +376,19 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
     }
     pc.n_tiles = toff;
     pc.inv64.assign(pc.n_tiles * kTile * kTile, 0.0);
+    const bool b16 = pc.local_prec == PDG_BF16;
+    if (b16) {
+        int64_t rows = 0, loc_tiles = 0;
+        pc.rbase.assign(pc.n_sub, 0);
+        for (int s = 0; s < pc.n_sub; ++s) {
+            pc.rbase[s] = rows;
+            rows += pc.sys[s].nt * kTile;
+            loc_tiles += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
+        }
+        pc.dscale.assign(rows, 0.0f);
+        pc.tiles_b16.assign(loc_tiles * kTile * kTile, 0);
+        pc.fallback.assign(pc.n_sub, 0);
+    }
 
     // local inverses (parallel over subdomains)
     parallel_for(pc.n_sub, [&](int64_t s) {
@@ -352,7 +407,13 @@ void setup_precond(const Mesh &m, const Bsr &K, const std::vector<double> &Mblk,
         }
         spd_inverse(ni, D.data());
         store_tiles(D.data(), ni, &pc.inv64[pc.sys[s].tile_off * kTile * kTile]);
+        if (b16)  // local tiles come first, so tile_off is also the offset in the local store
+            pc.fallback[s] = bf16_scaled_tiles(D.data(), ni, bf16_margin, &pc.dscale[pc.rbase[s]],
+                                               &pc.tiles_b16[pc.sys[s].tile_off * kTile * kTile])
+                                 ? 0
+                                 : 1;
     }, n_threads);
+    if (b16) pc.n_fallback = (int)std::count(pc.fallback.begin(), pc.fallback.end(), 1);
     if (coarse) {
         // few coarse systems: threads inside each inverse; many: one each
         const int nt = n_threads <= 0 ? (int)std::max(1u, std::thread::hardware_concurrency()) : n_threads;
