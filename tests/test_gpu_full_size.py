@@ -108,7 +108,8 @@ def test_cfg3_precision_forms_against_oracle():
         c = solver.from_problem(pr, device=DEV, local_prec=prec, coarse_prec="f64" if prec == "f64" else "f32",
                                 options=opts)
         U, Up, Y = solver.initial_state(c, pr)
-        assert np.array_equal(N(U)[idx], U0o)
+        # the same per-element constants projected by each side's own code
+        assert np.abs(N(U)[idx] - U0o).max() <= 1e-12 * np.abs(U0o).max()
         info = c.step(U, Up, Y, None, pr.tol, pr.maxit)
         u1 = N(U)[idx]
         err = np.linalg.norm(u1 - U1o) / np.linalg.norm(U1o)
