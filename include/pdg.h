@@ -245,20 +245,30 @@ pdg_status pdg_set_option(pdg_ctx *ctx, int32_t option, int64_t value);
 pdg_status pdg_kernel_timing(pdg_ctx *ctx, int64_t *launches, double *total_ms,
                              double *bytes_per_launch);
 
-/* Autotuner: times the Schwarz apply for work items of 64, 96, 128, 192, 256,
- * 384, 512 and 1024 KiB of tiles (those whose items fit in 64 KiB of LDS) and
- * the SpMV with 1, 2, 4 and 8 wavefronts per block-row group, `reps` launches
- * each (1..1000), with HIP events on the context's stream, and keeps the
- * fastest of each.  The choice changes results only at rounding level: it
- * sets the work split, and with it the order in which Schwarz partials (and,
- * for blocks of up to 32 rows, SpMV wavefront partials) are added; runs with
- * the same choice stay bitwise equal.  Synchronises.  Call after
- * pdg_bind_workspace. */
+/* Autotuner of the work split (the batching form's tile and wavefront
+ * assignment; not part of the paper).  Every candidate is timed as whole PCG
+ * iterations: the four launches of an iteration back to back, `reps` (1..1000)
+ * iterations after two untimed ones, no host synchronisation between launches,
+ * on a synthetic system (fixed pseudo-random right-hand side, x0 = 0, tol = 0 so
+ * that no system stops while timed), with HIP events on the context's stream.
+ * Knobs, one at a time in this order: the Schwarz work-item size (64, 96, 128,
+ * 192, 256, 384 KiB of tiles), the split of the coarse-system items (1..4
+ * pieces of that size), the wavefronts per SpMV block-row group (1, 2, 4, 8).
+ * Each candidate is timed twice (two sweeps) and keeps its faster time; the
+ * current value is replaced only by a candidate more than 1 % faster.  The
+ * choice changes results only at rounding level: it sets the work split, and
+ * with it the order in which Schwarz partials (and, for blocks of up to 32
+ * rows, SpMV wavefront partials) are added; runs with the same choice stay
+ * bitwise equal.  Overwrites the internal PCG vectors; synchronises.  Call
+ * after pdg_bind_workspace, outside a solve.  PDG_EBREAKDOWN if the synthetic
+ * solve stopped while timed. */
 typedef struct {
-    int32_t item_kb;      /* chosen Schwarz work-item size (KiB) */
-    int32_t spmv_waves;   /* chosen wavefronts per SpMV group */
-    double schwarz_us;    /* mean Schwarz-apply kernel time at the choice */
-    double spmv_us;       /* mean SpMV kernel time at the choice */
+    int32_t item_kb;        /* chosen Schwarz work-item size (KiB) */
+    int32_t spmv_waves;     /* chosen wavefronts per SpMV group */
+    int32_t coarse_split;   /* chosen split of the coarse-system items */
+    int32_t candidates;     /* timed runs */
+    double iter_us_before;  /* mean PCG iteration time with the settings on entry */
+    double iter_us;         /* mean PCG iteration time at the choice */
 } pdg_tune_result;
 pdg_status pdg_autotune(pdg_ctx *ctx, int32_t reps, pdg_tune_result *out);
 

@@ -64,11 +64,13 @@ class PdgMlpDesc(ctypes.Structure):
 
 
 class PdgTuneResult(ctypes.Structure):
-    _fields_ = [("item_kb", c_int32), ("spmv_waves", c_int32), ("schwarz_us", c_double), ("spmv_us", c_double)]
+    _fields_ = [("item_kb", c_int32), ("spmv_waves", c_int32), ("coarse_split", c_int32),
+                ("candidates", c_int32), ("iter_us_before", c_double), ("iter_us", c_double)]
 
     def as_dict(self):
-        return {"item_kb": self.item_kb, "spmv_waves": self.spmv_waves, "schwarz_us": self.schwarz_us,
-                "spmv_us": self.spmv_us}
+        return {"item_kb": self.item_kb, "spmv_waves": self.spmv_waves, "coarse_split": self.coarse_split,
+                "candidates": self.candidates,
+                "iter_us_before": self.iter_us_before, "iter_us": self.iter_us}
 
 
 class PdgError(RuntimeError):

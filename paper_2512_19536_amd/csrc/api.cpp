@@ -74,6 +74,7 @@ struct pdg_ctx {
     int n_threads = 0;
     // options
     int true_resid = 0, chunk = 4, timing = 0, item_kb = 128, use_graph = 0, spmv_wpg = 4;
+    int coarse_split = 3;        // coarse-system items are cut to 1/coarse_split of the item size
     int prev_iters = 0;
     // host data
     Mesh mesh;
@@ -343,6 +344,7 @@ int sys_prec(const Precond &pc, size_t sidx) {
 // LDS one Schwarz workgroup may use; items are cut to fit it whatever the
 // requested size.
 constexpr size_t kSchwarzLdsMax = 65536;
+constexpr int kMaxCoarseSplit = 4;
 
 // Largest tile count per item whose LDS fits kSchwarzLdsMax.
 int64_t max_tiles_per_item(const pdg_ctx *c) {
@@ -373,7 +375,7 @@ int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
         const int64_t nt = pc.sys[sidx].nt;
         const int prec = sys_prec(pc, sidx);
         int64_t jc = std::max<int64_t>(1, ((int64_t)kb * 1024) / (kTile * kTile * (int64_t)tile_elem_bytes(prec)));
-        if (sidx >= pc.n_sub) jc = std::max<int64_t>(1, jc / 3);
+        if (sidx >= pc.n_sub) jc = std::max<int64_t>(1, jc / c->coarse_split);
         jc = std::min(jc, nj_cap);
         for (int64_t I = 0; I < nt; ++I) {
             const int64_t ntile = I + 1, nc = (ntile + jc - 1) / jc;
@@ -1158,7 +1160,11 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         build_group_ell(c);
         plan_chunks(c);
         plan_items(c, c->item_kb, false);
+        // room for the finest split the autotuner tries (64 KiB items, coarse items cut in four)
+        const int cs = c->coarse_split;
+        c->coarse_split = std::max(cs, kMaxCoarseSplit);
         c->items_reserved = std::max<int64_t>((int64_t)c->it_sys.size(), plan_items(c, std::min(c->item_kb, 64), true));
+        c->coarse_split = cs;
         c->r_owner.assign(c->n_sys, 0);
         for (int b = 0; b < c->n_sys; ++b) c->r_owner[b] = (int32_t)(c->sys_elem_ptr[b] * c->mesh.nd / 256);
         choose_reductions(c);
@@ -1766,83 +1772,129 @@ pdg_status pdg_autotune(pdg_ctx *c, int32_t reps, pdg_tune_result *out) {
     return guard(c, [&] {
         require_gpu(c);
         if (reps < 1 || reps > 1000) throw Error(PDG_EINVAL, "reps must be in 1..1000");
+        if (c->run.active) throw Error(PDG_ESTATE, "pdg_autotune: a solve is in progress");
         hipStream_t s = c->stream;
         HIPCHK(hipStreamSynchronize(s));
         drop_graph(c);
+        // synthetic system: b with entries from a fixed linear congruential
+        // sequence in [-1, 1), x0 = 0; tol = 0, so no system stops while timed
+        const int64_t N = c->mesh.n_elem * c->mesh.nd;
+        {
+            std::vector<double> hb(N), hx(N, 0.0);
+            uint64_t st = 0x9e3779b97f4a7c15ull;
+            for (int64_t i = 0; i < N; ++i) {
+                st = st * 6364136223846793005ull + 1442695040888963407ull;
+                hb[i] = (double)(st >> 11) * 0x1.0p-52 - 1.0;
+            }
+            HIPCHK(hipMemcpyAsync(vec(c, c->w.b), hb.data(), N * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(vec(c, c->w.z), hx.data(), N * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        auto time_ms = [&](auto &&body) {
-            body();  // warm-up
+        // mean time of one PCG iteration (the four launches back to back, no
+        // host synchronisation between them) after two untimed iterations;
+        // negative if a system stopped during the measurement
+        auto iter_ms = [&]() -> double {
+            pcg_begin(c, vec(c, c->w.z), vec(c, c->w.b), false, nullptr, nullptr, 0.0, 1 << 30);
+            c->run.active = false;
+            for (int k = 0; k < 2; ++k) launch_iteration(c, false);
             HIPCHK(hipEventRecord(e0, s));
-            for (int k = 0; k < reps; ++k) body();
+            for (int k = 0; k < reps; ++k) launch_iteration(c, false);
             HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, c->n_sys * sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            for (int b = 0; b < c->n_sys; ++b)
+                if (c->sc_host[b].done) return -1.0;
             return (double)ms / reps;
         };
-        pdg_tune_result res{};
-        try {
-            // Schwarz work-item size: the restriction shares are formed once,
-            // then only the Schwarz kernel is timed
-            DevScalars *sc = c->sc_apply;
-            double *r = vec(c, c->w.r);
-            HIPCHK(launch_status_reset(sc, c->n_sys, -1.0, 0, 0, s));
-            HIPCHK(launch_update(update_args(c, 1, vec(c, c->w.t), r, sc), s));
-            const int cand[] = {64, 96, 128, 192, 256, 384, 512, 1024};
-            int best_kb = c->item_kb;
-            double best = 1e300;
-            for (int kb : cand) {
-                if (plan_items(c, kb, true) > c->items_reserved) continue;
-                plan_items(c, kb, false);
-                upload_items(c);
-                const SchwarzArgs sa = schwarz_args(c, 0, r, sc);
-                double ms = 0.0;
-                for (int k = 0; k <= reps; ++k) {  // the first launch warms up
-                    launch_schwarz_plain(c, sa, e0, e1);
-                    HIPCHK(hipEventSynchronize(e1));
-                    float t = 0.f;
-                    HIPCHK(hipEventElapsedTime(&t, e0, e1));
-                    if (k > 0) ms += t / reps;
-                }
-                if (ms < best) {
-                    best = ms;
-                    best_kb = kb;
-                }
-            }
-            plan_items(c, best_kb, false);
+        auto apply_plan = [&](int kb, int cs) {
+            c->coarse_split = cs;
+            plan_items(c, kb, false);
             upload_items(c);
-            c->item_kb = best_kb;
+            c->item_kb = kb;
             choose_reductions(c);
-            res.item_kb = best_kb;
-            res.schwarz_us = best * 1e3;
-            // SpMV wavefronts per group
-            int best_w = c->spmv_wpg;
-            best = 1e300;
-            for (int wv : {1, 2, 4, 8}) {
-                c->dA.wpg = wv;
-                SpmvArgs a{};
-                a.mode = SPMV_PLAIN;
-                a.x = vec(c, c->w.p);
-                a.y = vec(c, c->w.t);
-                const double ms = time_ms([&] { HIPCHK(launch_spmv(c->dA, a, s)); });
-                if (ms < best) {
-                    best = ms;
-                    best_w = wv;
-                }
+        };
+        auto plan_fits = [&](int kb, int cs) {
+            const int old = c->coarse_split;
+            c->coarse_split = cs;
+            const int64_t n = plan_items(c, kb, true);
+            c->coarse_split = old;
+            return n <= c->items_reserved;
+        };
+        pdg_tune_result res{};
+        const int timing = c->timing;
+        c->timing = 0;
+        try {
+            int kb = c->item_kb, cs = c->coarse_split, wv = c->spmv_wpg;
+            const double t_start = std::min(iter_ms(), iter_ms());
+            if (t_start < 0) throw Error(PDG_EBREAKDOWN, "pdg_autotune: the synthetic solve stopped while timed");
+            double t_final = t_start;
+            int timed = 2;
+            // one knob at a time; each candidate is timed twice (in two sweeps)
+            // and keeps its faster time; the current value is replaced only by
+            // a candidate more than 1 % faster
+            auto sweep = [&](const std::vector<int> &vals, int cur, auto &&set) {
+                std::vector<double> t(vals.size(), 1e300);
+                for (int pass = 0; pass < 2; ++pass)
+                    for (size_t i = 0; i < vals.size(); ++i) {
+                        if (!set(vals[i])) continue;
+                        const double ms = iter_ms();
+                        ++timed;
+                        if (ms > 0) t[i] = std::min(t[i], ms);
+                    }
+                double t_cur = 1e300;
+                for (size_t i = 0; i < vals.size(); ++i)
+                    if (vals[i] == cur) t_cur = t[i];
+                int pick = cur;
+                double t_pick = t_cur;
+                for (size_t i = 0; i < vals.size(); ++i)
+                    if (t[i] < 0.99 * t_pick) {
+                        pick = vals[i];
+                        t_pick = t[i];
+                    }
+                set(pick);
+                if (t_pick < 1e300) t_final = t_pick;
+                return pick;
+            };
+            if (!c->no_precond) {
+                kb = sweep({64, 96, 128, 192, 256, 384}, kb, [&](int v) {
+                    if (!plan_fits(v, cs)) return false;
+                    apply_plan(v, cs);
+                    return true;
+                });
+                if (c->pc.q > 0)
+                    cs = sweep({1, 2, 3, 4}, cs, [&](int v) {
+                        if (!plan_fits(kb, v)) return false;
+                        apply_plan(kb, v);
+                        return true;
+                    });
             }
-            c->spmv_wpg = best_w;
-            c->dA.wpg = best_w;
-            res.spmv_waves = best_w;
-            res.spmv_us = best * 1e3;
+            wv = sweep({1, 2, 4, 8}, wv, [&](int v) {
+                c->spmv_wpg = v;
+                c->dA.wpg = v;
+                return true;
+            });
+            res.item_kb = kb;
+            res.coarse_split = cs;
+            res.spmv_waves = wv;
+            res.candidates = timed;
+            res.iter_us_before = t_start * 1e3;
+            res.iter_us = t_final * 1e3;
         } catch (...) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
+            c->prev_iters = 0;
+            c->timing = timing;
             throw;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        c->prev_iters = 0;
+        c->timing = timing;
         if (out) *out = res;
     });
 }

@@ -141,10 +141,14 @@ def test_autotune_keeps_the_solution():
     ctx.rhs(U, I, None, b)
     x0 = U.clone()
     i0 = ctx.solve(b, x0, 1e-10, 5000)
-    res = ctx.autotune(reps=3)
+    res = ctx.autotune(reps=10)
     print(f"[autotune] {res}", flush=True)
-    assert res["item_kb"] in (64, 96, 128, 192, 256, 384, 512, 1024) and res["spmv_waves"] in (1, 2, 4, 8)
-    assert res["schwarz_us"] > 0 and res["spmv_us"] > 0
+    assert res["item_kb"] in (64, 96, 128, 192, 256, 384) and res["spmv_waves"] in (1, 2, 4, 8)
+    assert res["coarse_split"] in (1, 2, 3, 4) and res["candidates"] >= 2
+    # whole PCG iterations are timed; the choice is kept only where it is
+    # faster, so the tuned iteration is not slower than the one on entry
+    # (beyond timing noise)
+    assert 0 < res["iter_us"] <= 1.05 * res["iter_us_before"]
     x1 = U.clone()
     i1 = ctx.solve(b, x1, 1e-10, 5000)
     assert abs(i1["iters"] - i0["iters"]) <= 1
