@@ -51,6 +51,7 @@ struct Ws {
     int spwg, upwg, chunk0, lanc, pucr, cbase;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
     int tfb, dsc, rbase, sysf32;  // BF16 local store: FP32 fallback tiles, scales, their offsets, flags
+    int idesc;                    // Schwarz item descriptors
 };
 
 // State of the PCG run in progress (between pcg_begin and pcg_end).
@@ -98,6 +99,9 @@ struct pdg_ctx {
     // Schwarz work items and tile rows
     std::vector<int32_t> it_sys, it_row, it_j0, it_nj, it_own, rt_item0, rt_k, rt_nt, dof_rt, coarse_rt0;
     std::vector<int64_t> rt_cbase;
+    // per dense system, as the Schwarz items need them (set at bind)
+    std::vector<int32_t> ds_n, ds_f32;
+    std::vector<int64_t> ds_toff, ds_cbase, ds_dof0, ds_rbase;
     int max_nj = 1;
     int64_t items_reserved = 0;
     int pre_pq = 0, pre_rz = 0;  // dot products pre-summed by the reduction kernel
@@ -453,6 +457,7 @@ void plan_layout(pdg_ctx *c) {
     w.itj0 = L.add(n_items * 4);
     w.itnj = L.add(n_items * 4);
     w.itown = L.add(n_items * 4);
+    w.idesc = L.add(n_items * sizeof(ItemDesc));
     w.rtit0 = L.add((n_rt + 1) * 4);
     w.dofrt = L.add(N * 4);
     w.itdot = L.add(n_items * 8);  // one share per Schwarz workgroup (at most one per item)
@@ -555,6 +560,24 @@ void upload(pdg_ctx *c, int item, const std::vector<T> &v) {
 
 void upload_items(pdg_ctx *c) {
     if ((int64_t)c->it_sys.size() > c->items_reserved) throw Error(PDG_EINVAL, "internal: item plan exceeds its slot");
+    std::vector<ItemDesc> desc(c->it_sys.size());
+    for (size_t k = 0; k < desc.size(); ++k) {
+        ItemDesc &d = desc[k];
+        const int s = c->it_sys[k];
+        d = ItemDesc{};
+        d.s = s;
+        d.I = c->it_row[k];
+        d.j0 = c->it_j0[k];
+        d.nj = c->it_nj[k];
+        d.owner = c->it_own[k];
+        d.n = c->ds_n[s];
+        d.toff = (int32_t)c->ds_toff[s];
+        d.cbase = (int32_t)c->ds_cbase[s];
+        d.dof0 = (int32_t)c->ds_dof0[s];
+        d.rbase = (int32_t)c->ds_rbase[s];
+        d.f32 = c->ds_f32[s];
+    }
+    upload(c, c->w.idesc, desc);
     upload(c, c->w.itsys, c->it_sys);
     upload(c, c->w.itrow, c->it_row);
     upload(c, c->w.itj0, c->it_j0);
@@ -614,6 +637,8 @@ SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) 
     a.r = r;
     a.r0part = wptr<double>(c, c->w.r0p);
     a.sc = sc;
+    a.item_desc = wptr<ItemDesc>(c, c->w.idesc);
+    a.n_sys_one = c->n_sys == 1 ? 1 : 0;
     if (c->pc.local_prec == PDG_BF16) {
         a.dscale = wptr<float>(c, c->w.dsc);
         a.sys_rbase = wptr<int64_t>(c, c->w.rbase);
@@ -1332,6 +1357,14 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.sysnt, sys_nt);
         upload(c, w.systoff, sys_toff);
         upload(c, w.syscb, sys_cb);
+        // the item descriptors hold these in 32 bits
+        const int64_t lim = (int64_t)1 << 31;
+        if (pc.n_tiles >= lim || m.n_elem * nd >= lim) throw Error(PDG_EINVAL, "problem too large for 32-bit tile or dof indices");
+        c->ds_n = sys_n;
+        c->ds_toff = sys_toff;
+        c->ds_cbase = sys_cb;
+        c->ds_f32 = sys_f32;
+        c->ds_rbase = rbase;
         // subdomains whose elements form one contiguous run gather r directly
         std::vector<int64_t> sys_dof0(pc.sys.size(), -1);
         for (int sidx = 0; sidx < pc.n_sub; ++sidx) {
@@ -1341,6 +1374,7 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
             if (contiguous) sys_dof0[sidx] = (int64_t)pc.sub_elems[a0] * nd;
         }
         upload(c, w.sysdof0, sys_dof0);
+        c->ds_dof0 = sys_dof0;
         // tiles, converted to the storage precision
         const int64_t nloc = nloc_tiles * kTile * kTile;
         const int64_t ncoa = (int64_t)pc.inv64.size() - nloc;

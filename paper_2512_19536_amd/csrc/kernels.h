@@ -108,6 +108,19 @@ struct UpdateArgs {
     DevScalars *sc;
 };
 
+// Everything a Schwarz workgroup needs to know about its item, in one
+// 64-byte line: the item (system s, tile row I, tiles j0 .. j0 + nj - 1),
+// the batch system that owns it, and the dense system's size n, tile offset
+// in its store, global index of its first tile, first dof of a contiguous
+// subdomain (else -1), first row of its BF16 scales and its FP32-fallback
+// flag.
+struct alignas(64) ItemDesc {
+    int32_t s, I, j0, nj;
+    int32_t owner, n, toff, cbase;
+    int32_t dof0, rbase, f32, pad0;
+    int32_t pad1[4];
+};
+
 // Work item of the Schwarz kernel: stored tiles (I, J), J in [j0, j0 + nj),
 // of packed tile row I of dense system `sys` (a subdomain, or the coarse
 // system of one batch system; all J <= I).  Each stored tile is read once and
@@ -133,6 +146,8 @@ struct SchwarzArgs {
     const double *r;        // fine residual
     const double *r0part;   // per-chunk coarse restriction (summed on gather)
     DevScalars *sc;
+    const ItemDesc *item_desc;   // [n_items]
+    int n_sys_one;               // 1: one system in the context (its stop flag is sc[0])
     // BF16 local store only (else null): the stored tiles of local system s
     // hold C = D^{-1} K_s^{-1} D^{-1}; d of its row i is dscale[sys_rbase[s] + i].
     // Systems with sys_f32[s] = 1 are stored in FP32 in tiles_fallback instead

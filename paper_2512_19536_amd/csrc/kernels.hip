@@ -497,9 +497,10 @@ __device__ inline double sys_input(const SchwarzArgs &a, int s, bool coarse, int
 // the FP64 input entry of row I in *r_own (threads < 64), and in *dot_col the
 // thread's share of sum_J (x_J, column partial of J).
 template <typename E>
-__device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ tiles, int s, int I, int j0,
-                                    int nj, bool coarse, double *smem, int max_nj, double *yout,
-                                    double *r_own, double *dot_col) {
+__device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ tiles, const ItemDesc &d,
+                                    bool coarse, double *smem, int max_nj, double *yout, double *r_own,
+                                    double *dot_col) {
+    const int s = d.s, I = d.I, j0 = d.j0, nj = d.nj;
     using A = typename AccT<E>::T;
     using V = typename Ld<E>::V;
     constexpr int CW = 16 / sizeof(E);  // columns per 16-byte load
@@ -507,10 +508,10 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     constexpr int RG = 256 / NC;        // row groups
     constexpr int RPT = TILE / RG;      // rows per thread
     const int tid = threadIdx.x, cg = tid % NC, rg = tid / NC, lane = tid & 63, wv = tid >> 6;
-    const int n = a.sys_n[s];
-    const int64_t toff = a.sys_toff[s];
-    const int64_t cbase = a.sys_cbase[s] + (int64_t)I * (I + 1) / 2;
-    const int64_t dof0 = coarse ? -1 : a.sys_dof0[s];
+    const int n = d.n;
+    const int64_t toff = d.toff;
+    const int64_t cbase = d.cbase + (int64_t)I * (I + 1) / 2;
+    const int64_t dof0 = coarse ? -1 : d.dof0;
     // LDS: x in FP64 (columns, then row I), x in the accumulation type, column exchange
     double *x64 = smem;
     double *xI64 = x64 + max_nj * TILE;
@@ -548,7 +549,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     // BF16 tiles hold the scaled inverse C = D^{-1} K^{-1} D^{-1}: the products
     // run on D x and their results are scaled by D (rows past n have d = 0)
     constexpr bool kScaled = std::is_same<E, uint16_t>::value;
-    const float *ds = kScaled ? a.dscale + a.sys_rbase[s] : nullptr;
+    const float *ds = kScaled ? a.dscale + d.rbase : nullptr;
     // gather x over the item's tile columns and over tile row I
     const int base = j0 * TILE;
     for (int t = tid; t < nj * TILE; t += 256) {
@@ -683,11 +684,20 @@ template <typename EL, typename EC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SchwarzMinWaves<EL, EC>::value)))
 void k_schwarz(SchwarzArgs a, int max_nj) {
     const int item = blockIdx.x;
-    if (a.mode != 0 && a.sc[a.item_owner[item]].done) return;
+    // the item's descriptor (one 64-byte line) and, in a one-system context,
+    // that system's stop flag are read together: one memory round trip before
+    // the first tile request (a batch needs the owner first)
+    const ItemDesc d = a.item_desc[item];
+    if (a.mode != 0) {
+        int32_t done;
+        if (a.n_sys_one) done = a.sc[0].done;
+        else done = a.sc[d.owner].done;
+        if (done) return;
+    }
     extern __shared__ double smem[];
     __shared__ double yout[TILE];
     const int tid = threadIdx.x;
-    const int s = a.item_sys[item], I = a.item_row[item], j0 = a.item_j0[item], nj = a.item_nj[item];
+    const int s = d.s;
     const bool coarse = s >= a.n_sub;
     double r_own = 0.0, dcol = 0.0;
     const EL *tl = reinterpret_cast<const EL *>(a.tiles_local);
@@ -695,18 +705,18 @@ void k_schwarz(SchwarzArgs a, int max_nj) {
     if constexpr (std::is_same<EL, uint16_t>::value) {
         // BF16 local store: systems whose rounded inverse failed the
         // positive-definiteness check are stored in FP32
-        if (!coarse && a.sys_f32[s])
-            schwarz_item<float>(a, reinterpret_cast<const float *>(a.tiles_fallback), s, I, j0, nj, false, smem,
-                                max_nj, yout, &r_own, &dcol);
+        if (!coarse && d.f32)
+            schwarz_item<float>(a, reinterpret_cast<const float *>(a.tiles_fallback), d, false, smem, max_nj,
+                                yout, &r_own, &dcol);
         else if (!coarse)
-            schwarz_item<EL>(a, tl, s, I, j0, nj, false, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EL>(a, tl, d, false, smem, max_nj, yout, &r_own, &dcol);
         else
-            schwarz_item<EC>(a, tc, s, I, j0, nj, true, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EC>(a, tc, d, true, smem, max_nj, yout, &r_own, &dcol);
     } else {
         if (!coarse)
-            schwarz_item<EL>(a, tl, s, I, j0, nj, false, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EL>(a, tl, d, false, smem, max_nj, yout, &r_own, &dcol);
         else
-            schwarz_item<EC>(a, tc, s, I, j0, nj, true, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EC>(a, tc, d, true, smem, max_nj, yout, &r_own, &dcol);
     }
     if (tid < TILE) {
         const double y = yout[tid];
