@@ -52,6 +52,8 @@ struct Ws {
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
     int tfb, dsc, rbase, sysf32;  // BF16 local store: FP32 fallback tiles, scales, their offsets, flags
     int idesc;                    // Schwarz item descriptors
+    int updesc;                   // update workgroup records
+    int pblk, dsrc, bcsrc;        // p-update block records, fine and coarse value sources
 };
 
 // State of the PCG run in progress (between pcg_begin and pcg_end).
@@ -458,6 +460,11 @@ void plan_layout(pdg_ctx *c) {
     w.itnj = L.add(n_items * 4);
     w.itown = L.add(n_items * 4);
     w.idesc = L.add(n_items * sizeof(ItemDesc));
+    w.updesc = L.add(std::max<size_t>(1, c->upd_wg_c0.size()) * sizeof(UpdDesc));
+    const int64_t n_pblk = (N + 255) / 256;
+    w.pblk = L.add(std::max<int64_t>(1, n_pblk) * sizeof(PuBlk));
+    w.dsrc = L.add(std::max<int64_t>(1, N) * sizeof(ZSrc));
+    w.bcsrc = L.add(std::max<int64_t>(1, n_pblk * kPupdateKmax * std::max(pc.nq0, 1)) * sizeof(ZSrc));
     w.rtit0 = L.add((n_rt + 1) * 4);
     w.dofrt = L.add(N * 4);
     w.itdot = L.add(n_items * 8);  // one share per Schwarz workgroup (at most one per item)
@@ -578,6 +585,45 @@ void upload_items(pdg_ctx *c) {
         d.f32 = c->ds_f32[s];
     }
     upload(c, c->w.idesc, desc);
+    // p-update records (they name items, so they follow the item plan)
+    {
+        const int64_t nd = c->mesh.nd, N = c->mesh.n_elem * nd, nb = (N + 255) / 256;
+        const int nq = c->pc.q > 0 ? c->pc.nq0 : 0;
+        auto src = [&](int32_t rt_lane) {
+            const int rt = rt_lane >> 6;
+            ZSrc z{};
+            z.it0 = c->rt_item0[rt];
+            z.cb = (int32_t)c->rt_cbase[rt];
+            z.knt = (c->rt_k[rt] << 16) | c->rt_nt[rt];
+            z.nl = ((c->rt_item0[rt + 1] - c->rt_item0[rt]) << 8) | (rt_lane & 63);
+            return z;
+        };
+        std::vector<ZSrc> ds(N);
+        for (int64_t i = 0; i < N; ++i) ds[i] = src(c->dof_rt[i]);
+        const std::vector<int32_t> cr = pupdate_coarse_ranges(c), cbase = coarse_value_base(c);
+        std::vector<PuBlk> bl(nb);
+        std::vector<ZSrc> cs(std::max<int64_t>(1, nb * kPupdateKmax * std::max(nq, 1)));
+        for (int64_t k = 0; k < nb; ++k) {
+            PuBlk &b = bl[k];
+            const int64_t i0 = k * 256, i1 = std::min(N, i0 + 256) - 1;
+            b.s_lo = c->elem_sys[i0 / nd];
+            b.s_hi = c->elem_sys[i1 / nd];
+            b.c_lo = cr[2 * k];
+            b.n_c = cr[2 * k + 1];
+            b.it0 = c->r_item[b.s_lo];
+            b.it1 = c->r_item[b.s_lo + 1];
+            b.u0 = c->r_upd[b.s_lo];
+            b.u1 = c->r_upd[b.s_lo + 1];
+            if (nq > 0 && b.n_c <= kPupdateKmax)
+                for (int t = 0; t < b.n_c * nq; ++t) {
+                    const int gi = cbase[b.c_lo + t / nq] + t % nq;
+                    cs[k * kPupdateKmax * nq + t] = src(gi);
+                }
+        }
+        upload(c, c->w.dsrc, ds);
+        upload(c, c->w.pblk, bl);
+        upload(c, c->w.bcsrc, cs);
+    }
     upload(c, c->w.itsys, c->it_sys);
     upload(c, c->w.itrow, c->it_row);
     upload(c, c->w.itj0, c->it_j0);
@@ -718,6 +764,7 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
     u.lcap = c->lcap;
     u.rng = ranges(c);
     u.sc = sc;
+    u.wg_desc = wptr<UpdDesc>(c, c->w.updesc);
     return u;
 }
 
@@ -746,6 +793,9 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, const double *r, Dev
     p.rrpart = wptr<double>(c, c->w.rrpart);
     p.bbpart = wptr<double>(c, c->w.part);
     p.rng = ranges(c);
+    p.blk = wptr<PuBlk>(c, c->w.pblk);
+    p.dof_src = wptr<ZSrc>(c, c->w.dsrc);
+    p.blk_csrc = wptr<ZSrc>(c, c->w.bcsrc);
     p.p = out;
     p.lanczos = sc == c->sc ? wptr<double2>(c, c->w.lanc) : nullptr;
     p.lcap = c->lcap;
@@ -1422,6 +1472,24 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.cbase, coarse_value_base(c));
         upload(c, w.grpptr, c->grp_ptr);
         upload(c, w.grpel, c->grp_elems);
+        {
+            // update workgroup records (chunks, system, SpMV partial range, first chunk)
+            std::vector<UpdDesc> ud(c->upd_wg_c0.size() - 1);
+            for (size_t k = 0; k < ud.size(); ++k) {
+                UpdDesc &d = ud[k];
+                d.c_begin = c->upd_wg_c0[k];
+                d.c_end = c->upd_wg_c0[k + 1];
+                d.b = c->upd_sys[d.c_begin];
+                d.g0 = c->r_spmv[d.b];
+                d.g1 = c->r_spmv[d.b + 1];
+                d.f_e0 = c->grp_ptr[d.c_begin];
+                d.f_n = c->grp_ptr[d.c_begin + 1] - d.f_e0;
+                bool run = true;
+                for (int k2 = 1; k2 < d.f_n && run; ++k2) run = c->grp_elems[d.f_e0 + k2] == c->grp_elems[d.f_e0] + k2;
+                d.e_first = run ? c->grp_elems[d.f_e0] : -1;
+            }
+            upload(c, w.updesc, ud);
+        }
         upload(c, w.upsys, c->upd_sys);
         upload(c, w.cchunk, c->cchunk_ptr);
         for (int k : {w.sc, w.sca})

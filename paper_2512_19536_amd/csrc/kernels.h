@@ -88,6 +88,14 @@ struct SpmvArgs {
     DevScalars *sc;         // [n_sys]
 };
 
+// What an update workgroup needs first, in one 32-byte record: its chunks
+// [c_begin, c_end), its system b and that system's SpMV workgroups
+// [g0, g1), and its first chunk: elements grp_elems[f_e0 .. f_e0 + f_n) of
+// grp_ptr, which are the run e_first .. e_first + f_n - 1 if e_first >= 0.
+struct alignas(32) UpdDesc {
+    int32_t c_begin, c_end, b, g0, g1, f_e0, f_n, e_first;
+};
+
 struct UpdateArgs {
     int init;               // 1: no x/r update (iteration 0)
     int pre_pq;             // 1: take (p, q) from sc.pq_sum instead of summing the SpMV partials
@@ -106,6 +114,7 @@ struct UpdateArgs {
     int lcap;
     SysRanges rng;
     DevScalars *sc;
+    const UpdDesc *wg_desc; // [n_wg]
 };
 
 // Everything a Schwarz workgroup needs to know about its item, in one
@@ -165,6 +174,22 @@ struct SchwarzArgs {
 // Coarse elements whose values a p-update block keeps in LDS.
 constexpr int kPupdateKmax = 8;
 
+// Where one value of z = B r is assembled from (a tile row of a dense system
+// and a row inside it), in one 16-byte record: the first of the tile row's
+// nit items, the global index cb of the dense system's first tile, the
+// tile row K inside the system and the system's nt tile rows, the row lane.
+struct alignas(16) ZSrc {
+    int32_t it0, cb, knt /* K << 16 | nt */, nl /* nit << 8 | lane */;
+};
+
+// Per p-update block (256 dofs), in one 32-byte record: the batch systems of
+// its first and last dof, the coarse elements its dofs touch (first and
+// count, or kPupdateKmax + 1), and the Schwarz-item and update-workgroup
+// ranges of its first system.
+struct alignas(32) PuBlk {
+    int32_t s_lo, s_hi, c_lo, n_c, it0, it1, u0, u1;
+};
+
 struct PupdateArgs {
     int mode;               // 0: out = z; 1: PCG init, p = z; 2: PCG, p = z + beta p
     int pre_rz;             // 1: take (r, z) from sc.rz_sum instead of summing the Schwarz shares
@@ -192,6 +217,9 @@ struct PupdateArgs {
     double2 *lanczos;            // [n_sys][lcap] (alpha_j, beta_j), or null
     int lcap;
     DevScalars *sc;
+    const PuBlk *blk;            // [blocks]
+    const ZSrc *dof_src;         // [N] fine value of every dof
+    const ZSrc *blk_csrc;        // [blocks][kPupdateKmax * nq0] coarse values kept by each block
 };
 
 struct IonicArgs {

@@ -293,13 +293,16 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv_wide(DevMatrix A, SpmvArgs a)
 template <int ND, int NQ>
 __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
     const int wg = blockIdx.x;
-    const int c_begin = a.wg_c0[wg], c_end = a.wg_c0[wg + 1];
-    const int b = a.grp_sys[c_begin];
+    // the workgroup's record first (one load): chunks, system, SpMV
+    // partials and the first chunk's elements
+    const UpdDesc dsc = a.wg_desc[wg];
+    const int c_begin = dsc.c_begin, c_end = dsc.c_end;
+    const int b = dsc.b;
     DevScalars *sc = a.sc + b;
     constexpr int NV = NQ > 0 ? NQ : 1;
     // The thread's first dof (usually its only one) is read before the
     // reductions below, which do not change it, so the latencies overlap.
-    const int f_e0 = a.grp_ptr[c_begin], f_n = (a.grp_ptr[c_begin + 1] - f_e0) * ND;
+    const int f_e0 = dsc.f_e0, f_n = dsc.f_n * ND;
     const bool f_has = (int)threadIdx.x < f_n;
     int64_t f_idx = 0;
     double f_r = 0.0, f_p = 0.0, f_q = 0.0, f_x = 0.0, f_P[NV];
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
     for (int k = 0; k < NV; ++k) f_P[k] = 0.0;
     if (f_has) {
         const int le = threadIdx.x / ND, i = threadIdx.x - le * ND;
-        f_idx = (int64_t)a.grp_elems[f_e0 + le] * ND + i;
+        f_idx = (int64_t)(dsc.e_first >= 0 ? dsc.e_first + le : a.grp_elems[f_e0 + le]) * ND + i;
         f_r = a.r[f_idx];
         if (!a.init) {
             f_p = a.p[f_idx];
@@ -322,9 +325,9 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
     if (block_bcast<128>(threadIdx.x == 0 ? sc->done : 0)) return;
     double alpha = 0.0;
     if (!a.init) {
-        const int g0 = a.rng.spmv[b];
+        const int g0 = dsc.g0;
         const double pq = a.pre_pq ? sc->pq_sum
-                                   : block_sum_partials<128>(a.pqpart + 2 * (int64_t)g0, a.rng.spmv[b + 1] - g0, 2, 0);
+                                   : block_sum_partials<128>(a.pqpart + 2 * (int64_t)g0, dsc.g1 - g0, 2, 0);
         const int j = sc->iters + 1;
         alpha = sc->rz[(j - 1) & 1] / pq;
         if (wg == a.rng.upd[b] && threadIdx.x == 0) {
@@ -343,7 +346,10 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
     }
     double rr = 0.0;
     for (int c = c_begin; c < c_end; ++c) {
-        const int e0 = a.grp_ptr[c], ndof = (a.grp_ptr[c + 1] - e0) * ND;
+        const bool first_c = c == c_begin;
+        const int e0 = first_c ? f_e0 : a.grp_ptr[c];
+        const int ndof = first_c ? f_n : (a.grp_ptr[c + 1] - e0) * ND;
+        const int e_first = first_c ? dsc.e_first : -1;
         double v[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] = 0.0;
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
                 for (int j = 0; j < NV; ++j) Pr[j] = f_P[j];
             } else {
                 const int le = d / ND, i = d - le * ND;
-                idx = (int64_t)a.grp_elems[e0 + le] * ND + i;
+                idx = (int64_t)(e_first >= 0 ? e_first + le : a.grp_elems[e0 + le]) * ND + i;
                 rv = a.r[idx];
                 if (!a.init) {
                     pv = a.p[idx];
@@ -748,6 +754,10 @@ __device__ inline TileRow tile_row(const PupdateArgs &a, int rt) {
     return TileRow{a.rt_item0[rt], a.rt_item0[rt + 1], a.rt_k[rt], a.rt_nt[rt], a.rt_cbase[rt]};
 }
 
+__device__ inline TileRow tile_row(const ZSrc &z) {
+    return TileRow{z.it0, z.it0 + (z.nl >> 8), z.knt >> 16, z.knt & 0xffff, (int64_t)z.cb};
+}
+
 __device__ inline double tile_row_value(const PupdateArgs &a, const TileRow &t, int lane) {
     double v = 0.0;
     for (int it = t.it0; it < t.it1; ++it) v += a.part[(int64_t)it * TILE + lane];
@@ -779,9 +789,10 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const int nd = a.nd;
     const int64_t n = a.n_elem * nd;
     const int64_t i0 = (int64_t)blockIdx.x * 256;
-    const int64_t i1 = (i0 + 256 < n ? i0 + 256 : n) - 1;
     const int64_t idx = i0 + threadIdx.x;
-    const int my = idx < n ? a.elem_sys[idx / nd] : -1;
+    // the block's record, and each dof's source record, are read at once
+    const PuBlk bk = a.blk[blockIdx.x];
+    const int my = idx < n ? (bk.s_lo == bk.s_hi ? bk.s_lo : a.elem_sys[idx / nd]) : -1;
     // z = B r depends only on the Schwarz partials, not on this launch's
     // reductions, so it is formed first (for every dof of the block, also of
     // systems that turn out to be done; those values are dropped) and its
@@ -791,9 +802,9 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     int f_lane = 0;
     TileRow f_tr{0, 0, 0, 0, 0};
     if (my >= 0 && !a.r_ident) {
-        const int dr = a.dof_rt[idx];
-        f_lane = dr & 63;
-        f_tr = tile_row(a, dr >> 6);
+        const ZSrc zs = a.dof_src[idx];
+        f_lane = zs.nl & 63;
+        f_tr = tile_row(zs);
     }
     // coarse values z0 of the block's coarse elements, once per block: the
     // block's elements usually lie in one or two coarse elements (numbered
@@ -803,13 +814,12 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     __shared__ double s_z0[KMAX * (NQ > 0 ? NQ : 1)];
     int c_lo = 0, n_c = KMAX + 1;
     if (NQ > 0) {
-        c_lo = a.blk_crange[2 * blockIdx.x];
-        n_c = a.blk_crange[2 * blockIdx.x + 1];
+        c_lo = bk.c_lo;
+        n_c = bk.n_c;
         if (n_c <= KMAX) {
             for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
-                const int c = c_lo + t / NQ, j = t % NQ;
-                const int gi = a.coarse_base[c] + j;
-                s_z0[t] = tile_row_value(a, gi >> 6, gi & 63);
+                const ZSrc zs = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NQ) + t];
+                s_z0[t] = tile_row_value(a, tile_row(zs), zs.nl & 63);
             }
             __syncthreads();
         }
@@ -842,13 +852,14 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     bool active = a.mode == 0 && my >= 0;
     if (a.mode != 0) {
         // every system with dofs in this block, in turn
-        const int s_lo = a.elem_sys[i0 / nd], s_hi = a.elem_sys[i1 / nd];
+        const int s_lo = bk.s_lo, s_hi = bk.s_hi;
         for (int b = s_lo; b <= s_hi; ++b) {
             DevScalars *sc = a.sc + b;
             // the owner block may set `done` during this launch
             if (block_bcast<256>(threadIdx.x == 0 ? sc->done : 0)) continue;
-            const int it0 = a.r_ident ? a.rng.upd[b] : a.rng.item[b];
-            const int it1 = a.r_ident ? a.rng.upd[b + 1] : a.rng.item[b + 1];
+            const bool first = b == s_lo;
+            const int it0 = a.r_ident ? (first ? bk.u0 : a.rng.upd[b]) : (first ? bk.it0 : a.rng.item[b]);
+            const int it1 = a.r_ident ? (first ? bk.u1 : a.rng.upd[b + 1]) : (first ? bk.it1 : a.rng.item[b + 1]);
             const double rz = a.pre_rz ? sc->rz_sum
                                        : block_sum_partials<256>(a.r_ident ? a.rrpart + it0 : a.itemdot + it0,
                                                                  it1 - it0, 1, 0);
@@ -860,8 +871,8 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
             }
             if (a.rng.owner[b] != (int)blockIdx.x) continue;
             // owner: close iteration j of system b
-            const int u0 = a.rng.upd[b];
-            const double rr = block_sum_partials<256>(a.rrpart + u0, a.rng.upd[b + 1] - u0, 1, 0);
+            const int u0 = first ? bk.u0 : a.rng.upd[b];
+            const double rr = block_sum_partials<256>(a.rrpart + u0, (first ? bk.u1 : a.rng.upd[b + 1]) - u0, 1, 0);
             double bb = 0.0;
             if (a.mode == 1) {
                 const int g0 = a.rng.spmv[b];
