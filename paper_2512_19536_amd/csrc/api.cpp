@@ -54,6 +54,7 @@ struct Ws {
     int idesc;                    // Schwarz item descriptors
     int updesc;                   // update workgroup records
     int pblk, dsrc, bcsrc;        // p-update block records, fine and coarse value sources
+    int spdesc;                   // SpMV workgroup records
 };
 
 // State of the PCG run in progress (between pcg_begin and pcg_end).
@@ -501,6 +502,7 @@ void plan_layout(pdg_ctx *c) {
     w.ritem = L.add((n_sys + 1) * 4);
     w.rowner = L.add(n_sys * 4);
     w.spwg = L.add(c->spmv_wg_g0.size() * 4);
+    w.spdesc = L.add(std::max<size_t>(1, c->spmv_wg_g0.size()) * sizeof(SpDesc));
     w.upwg = L.add(c->upd_wg_c0.size() * 4);
     w.chunk0 = L.add(n_sys * 4);
     w.x = L.add(N * 8);
@@ -1370,6 +1372,18 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.rupd, c->r_upd);
         upload(c, w.rowner, c->r_owner);
         upload(c, w.spwg, c->spmv_wg_g0);
+        {
+            std::vector<SpDesc> sd(c->spmv_wg_g0.size() - 1);
+            for (size_t k = 0; k < sd.size(); ++k) {
+                SpDesc &d = sd[k];
+                d.g_begin = c->spmv_wg_g0[k];
+                d.g_end = c->spmv_wg_g0[k + 1];
+                d.sys = c->grp_sys[d.g_begin];
+                d.s0 = c->grp_slot_off[d.g_begin];
+                d.s1 = c->grp_slot_off[d.g_begin + 1];
+            }
+            upload(c, w.spdesc, sd);
+        }
         upload(c, w.upwg, c->upd_wg_c0);
         upload(c, w.chunk0, std::vector<int32_t>(c->r_chunk.begin(), c->r_chunk.end() - 1));
         upload(c, w.elsys, c->elem_sys);
@@ -1512,6 +1526,8 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         c->dA.grp_sys = wptr<int32_t>(c, w.gsys);
         c->dA.wg_g0 = wptr<int32_t>(c, w.spwg);
         c->dA.n_wg = (int)c->spmv_wg_g0.size() - 1;
+        c->dA.wg_desc = wptr<SpDesc>(c, w.spdesc);
+        c->dA.one_sys = c->n_sys == 1 ? 1 : 0;
         c->sc = wptr<DevScalars>(c, w.sc);
         c->sc_apply = wptr<DevScalars>(c, w.sca);
         c->state = S_BOUND;

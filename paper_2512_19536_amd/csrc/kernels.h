@@ -56,6 +56,14 @@ struct SysRanges {
     const int32_t *owner;   // [n_sys] p-update workgroup holding the system's first dof
 };
 
+// What an SpMV workgroup needs first, in one 32-byte record: its groups
+// [g_begin, g_end), their system, and the slot range [s0, s1) of its first
+// group.
+struct alignas(32) SpDesc {
+    int32_t g_begin, g_end, sys, pad0;
+    int64_t s0, s1;
+};
+
 // Matrix in interleaved group-ELL form (see the SpMV kernel).
 struct DevMatrix {
     int nd, G;              // block size, block rows per group
@@ -70,6 +78,8 @@ struct DevMatrix {
     const int32_t *grp_sys;      // [n_groups] system of each group
     const int32_t *wg_g0;        // [n_wg+1] groups of each workgroup (contiguous, one system)
     int n_wg;
+    const SpDesc *wg_desc;       // [n_wg]
+    int one_sys;                 // 1: one system (its stop flag is sc[0])
 };
 
 enum SpmvMode { SPMV_PLAIN = 0, SPMV_PQ = 1, SPMV_RESID = 2, SPMV_STEP = 3, SPMV_RHS = 4 };

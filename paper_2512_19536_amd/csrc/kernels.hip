@@ -154,8 +154,16 @@ __device__ inline void spmv_out(const DevMatrix &A, const SpmvArgs &a, int row, 
 template <int ND, int WPG, bool NT>
 __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     constexpr int G = ND <= 64 ? 64 / ND : 1;
-    const int64_t g_begin = A.wg_g0[blockIdx.x], g_end = A.wg_g0[blockIdx.x + 1];
-    if (a.mode == SPMV_PQ && a.sc[A.grp_sys[g_begin]].done) return;
+    // the workgroup's record (and, in a one-system context, the stop flag)
+    // first: one memory round trip before the first slot's loads
+    const SpDesc dsc = A.wg_desc[blockIdx.x];
+    const int64_t g_begin = dsc.g_begin, g_end = dsc.g_end;
+    if (a.mode == SPMV_PQ) {
+        int32_t done;
+        if (A.one_sys) done = a.sc[0].done;
+        else done = a.sc[dsc.sys].done;
+        if (done) return;
+    }
     __shared__ double s_acc[2][WPG][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane / ND, i = lane - (lane / ND) * ND;
@@ -166,8 +174,11 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
     int par = 0;
     for (int64_t g = g_begin; g < g_end; ++g) {
         double acc = 0.0;
+        // the output row, requested before the products
+        const int row = (w == 0 && r < G) ? A.grp_rows[g * G + r] : -1;
         if (r < G) {
-            const int64_t s0 = A.grp_slot_off[g], ns = A.grp_slot_off[g + 1] - s0;
+            const int64_t s0 = g == g_begin ? dsc.s0 : A.grp_slot_off[g];
+            const int64_t ns = (g == g_begin ? dsc.s1 : A.grp_slot_off[g + 1]) - s0;
             const int32_t *colp = A.grp_col + s0 * G + r;
             const double *vp = A.grp_val + s0 * G * ND * ND + lane;
             double accu[U];
@@ -211,7 +222,6 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv(DevMatrix A, SpmvArgs a) {
             par ^= 1;
         }
         if (w != 0) continue;  // wave 0 finishes the group
-        const int row = (r < G) ? A.grp_rows[g * G + r] : -1;
         if (row < 0) continue;
         spmv_out<ND>(A, a, row, i, acc, part);
     }
@@ -238,12 +248,20 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv_wide(DevMatrix A, SpmvArgs a)
     constexpr int T = CH * ND;
     constexpr int STEPS = (T + 63) / 64;
     __shared__ double s_p[T];
-    const int64_t g_begin = A.wg_g0[blockIdx.x], g_end = A.wg_g0[blockIdx.x + 1];
-    if (a.mode == SPMV_PQ && a.sc[A.grp_sys[g_begin]].done) return;
+    const SpDesc dsc = A.wg_desc[blockIdx.x];
+    const int64_t g_begin = dsc.g_begin, g_end = dsc.g_end;
+    if (a.mode == SPMV_PQ) {
+        int32_t done;
+        if (A.one_sys) done = a.sc[0].done;
+        else done = a.sc[dsc.sys].done;
+        if (done) return;
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double part[2] = {0.0, 0.0};
     for (int64_t g = g_begin; g < g_end; ++g) {
-        const int64_t s0 = A.grp_slot_off[g], ns = A.grp_slot_off[g + 1] - s0;
+        const int64_t s0 = g == g_begin ? dsc.s0 : A.grp_slot_off[g];
+        const int64_t ns = (g == g_begin ? dsc.s1 : A.grp_slot_off[g + 1]) - s0;
+        const int row = (w == 0 && lane < ND) ? A.grp_rows[g] : -1;
         const int32_t *colp = A.grp_col + s0;
         const double *vp = A.grp_val + s0 * ND * ND;
         double acc = 0.0;
@@ -273,7 +291,6 @@ __global__ __launch_bounds__(64 * WPG) void k_spmv_wide(DevMatrix A, SpmvArgs a)
             __syncthreads();
         }
         if (w != 0 || lane >= ND) continue;
-        const int row = A.grp_rows[g];
         if (row >= 0) spmv_out<ND>(A, a, row, lane, acc, part);
     }
     if (w != 0 || a.mode == SPMV_PLAIN || a.mode == SPMV_RHS) return;
