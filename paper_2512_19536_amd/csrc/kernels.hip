@@ -1141,7 +1141,9 @@ struct NB { static constexpr int v = DIM == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) 
 
 // One wavefront per element.  Pass 1: G_l = int m_l(u^k, y^k) phi and
 // Y^(k+1) = Y^k - dt M^{-1} G (second line of eq. (4)).  Pass 2: the ion term
-// I = int f(u~, y^(k+1)) phi with u~ = (3 u^k - u^(k-1)) / 2.
+// I = int f(u~, y^(k+1)) phi with the extrapolated potential
+// u~ = ext_now u^k + ext_prev u^(k-1) (2, -1: to t^(k+1); 3/2, -1/2: to the
+// Crank-Nicolson mid-point).
 template <int DIM, int P>
 __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
     constexpr int ND = NB<DIM, P>::v;
