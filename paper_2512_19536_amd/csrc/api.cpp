@@ -1247,18 +1247,19 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
         choose_reductions(c);
         // algorithmic bytes of one Schwarz apply: the rows of the stored tiles
         // that hold dofs (the last tile row of a system is zero-padded), below
-        // the diagonal in full and of each diagonal tile the 16-byte pieces that
-        // reach its diagonal; plus input gathers and outputs
+        // the diagonal in full and of each diagonal tile the pieces (16 bytes,
+        // 8 for BF16 tiles) that reach its diagonal; plus input gathers and outputs
         int64_t tile_bytes = 0;
         for (size_t sidx = 0; sidx < c->pc.sys.size(); ++sidx) {
             const DenseSys &S = c->pc.sys[sidx];
             const int64_t es = (int64_t)tile_elem_bytes(sys_prec(c->pc, sidx));
-            const int cw = (int)(16 / es);
+            const int piece = es == 2 ? 8 : 16;  // bytes per lane load (BF16 tiles: 8)
+            const int cw = (int)(piece / es);
             for (int64_t I = 0; I < S.nt; ++I) {
                 const int rows = (int)std::min<int64_t>(kTile, S.n - I * kTile);
                 int64_t diag_pieces = 0;
                 for (int r = 0; r < rows; ++r) diag_pieces += r / cw + 1;
-                tile_bytes += I * rows * kTile * es + diag_pieces * 16;
+                tile_bytes += I * rows * kTile * es + diag_pieces * piece;
             }
         }
         const int64_t N = c->mesh.n_elem * c->mesh.nd;

@@ -425,7 +425,7 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
 // (row-major inside a tile).  A workgroup (256 threads) owns one work item:
 // the stored tiles (I, J), J in [j0, j0 + nj), of one packed tile row I of
 // one system; each tile is read once and used for both of its products
-// (see schwarz_item).  Each thread loads 16 bytes per tile row for RPT rows,
+// (see schwarz_item).  Each thread loads 16 bytes (8 for BF16) per tile row for RPT rows,
 // so every load instruction of a wavefront reads whole contiguous tile rows.
 // Items hold ~128 KiB of tiles by default, so the grid is many similar-sized
 // workgroups.
@@ -434,7 +434,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <typename E> struct AccT { using T = float; };
 template <> struct AccT<double> { using T = double; };
 
-// 16-byte load type per storage type; element c of a loaded vector as the
+// Load type per storage type; element c of a loaded vector as the
 // accumulation type.
 template <typename E> struct Ld;
 template <> struct Ld<double> {
@@ -447,13 +447,28 @@ template <> struct Ld<float> {
         return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
     }
 };
+// BF16 tiles are read 8 bytes (4 columns) per lane: with 16 columns per row
+// group the column sums need one shuffle round fewer, and 4 columns instead
+// of 8 per round, than with 16-byte loads.
 template <> struct Ld<uint16_t> {
-    using V = uint4;
+    using V = uint2;
     static __device__ inline float get(const V &v, int c) {
-        const uint32_t w = (c >> 1) == 0 ? v.x : ((c >> 1) == 1 ? v.y : ((c >> 1) == 2 ? v.z : v.w));
+        const uint32_t w = (c >> 1) == 0 ? v.x : v.y;
         return __uint_as_float((c & 1) ? (w & 0xffff0000u) : (w << 16));
     }
 };
+
+// Bytes one lane loads per tile row piece, and the columns they hold.
+template <typename E> struct Piece { static constexpr int bytes = 16; };
+template <> struct Piece<uint16_t> { static constexpr int bytes = 8; };
+template <typename E> __device__ inline typename Ld<E>::V load_piece(const E *p) {
+    using V = typename Ld<E>::V;
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    if constexpr (Piece<E>::bytes == 16)
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p)));
+    else
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p)));
+}
 
 // Multiply-accumulate of one 64x64 tile held in registers (RPT rows of CW
 // columns per thread): tile (I, J) as stored (J <= I) or transposed (J > I).
@@ -526,7 +541,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     const int s = d.s, I = d.I, j0 = d.j0, nj = d.nj;
     using A = typename AccT<E>::T;
     using V = typename Ld<E>::V;
-    constexpr int CW = 16 / sizeof(E);  // columns per 16-byte load
+    constexpr int CW = Piece<E>::bytes / sizeof(E);  // columns per load
     constexpr int NC = TILE / CW;       // column groups per tile row
     constexpr int RG = 256 / NC;        // row groups
     constexpr int RPT = TILE / RG;      // rows per thread
@@ -546,7 +561,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     };
     // Tiles are read once per apply and exceed the last-level cache: non-temporal
     // loads keep them from evicting data that is reused (the SpMV matrix).  Of
-    // the diagonal tile only the 16-byte pieces that reach the diagonal are read,
+    // the diagonal tile only the pieces that reach the diagonal are read,
     // and rows past the system's last dof (zero padding) are not read at all.
     const int rows_left = n - I * TILE;
     auto load = [&](V (&buf)[RPT], int J) {
@@ -556,8 +571,8 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         for (int k = 0; k < RPT; ++k) {
             const int r = rg * RPT + k;
             buf[k] = (r < rows_left && (!diag || cg * CW <= r))
-                         ? __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tp + k * TILE)))
-                         : __builtin_bit_cast(V, u32x4{0u, 0u, 0u, 0u});
+                         ? load_piece<E>(tp + k * TILE)
+                         : V{};
         }
     };
     A accR[RPT];
@@ -1422,7 +1437,7 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t s) {
 
 template <typename E> static constexpr size_t acc_size() { return sizeof(typename AccT<E>::T); }
 template <typename E> static constexpr size_t scratch_bytes() {
-    constexpr int CW = 16 / sizeof(E), NC = TILE / CW, RG = 256 / NC, RPT = TILE / RG;
+    constexpr int CW = Piece<E>::bytes / sizeof(E), NC = TILE / CW, RG = 256 / NC, RPT = TILE / RG;
     return (size_t)256 * RPT * acc_size<E>();
 }
 
