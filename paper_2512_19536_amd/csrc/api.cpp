@@ -44,13 +44,13 @@ struct Layout {
 
 // Workspace slots (indices into Layout::items).
 struct Ws {
-    int grows, gslot, gcol, gval, gsys, mass, minv, qpptr, qpxi, qpw, norm, prm, subptr, subel;
-    int itsys, itrow, itj0, itnj, itown, rtit0, dofrt, itdot, rowpart;
-    int sysn, sysnt, systoff, sysdof0, syscb, rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
+    int grows, gslot, gcol, gval, mass, minv, qpptr, qpxi, qpw, norm, prm, subptr, subel;
+    int rtit0, itdot, rowpart;
+    int rtk, rtnt, rtcb, colp, tloc, tcoa, P, ecoa, elsys;
     int grpptr, grpel, upsys, cchunk, csys0, rspmv, rupd, ritem, rowner;
-    int spwg, upwg, chunk0, lanc, pucr, cbase;
+    int chunk0, lanc, cbase;
     int x, r, z, p, q, I, t, b, r0p, sc, sca, part, rrpart;
-    int tfb, dsc, rbase, sysf32;  // BF16 local store: FP32 fallback tiles, scales, their offsets, flags
+    int tfb, dsc;                 // BF16 local store: FP32 fallback tiles, scales
     int idesc;                    // Schwarz item descriptors
     int updesc;                   // update workgroup records
     int pblk, dsrc, bcsrc;        // p-update block records, fine and coarse value sources
@@ -445,7 +445,6 @@ void plan_layout(pdg_ctx *c) {
     w.gslot = L.add(c->grp_slot_off.size() * 8);
     w.gcol = L.add(c->grp_col.size() * 4);
     w.gval = L.add(c->grp_val.size() * 8);
-    w.gsys = L.add(c->grp_sys.size() * 4);
     w.mass = L.add(N * nd * 8);
     w.minv = L.add(N * nd * 8);
     w.qpptr = L.add((n + 1) * 8);
@@ -455,11 +454,6 @@ void plan_layout(pdg_ctx *c) {
     w.prm = L.add(kIonicParams * 8);
     w.subptr = L.add(pc.sub_ptr.size() * 4);
     w.subel = L.add(pc.sub_elems.size() * 4);
-    w.itsys = L.add(n_items * 4);
-    w.itrow = L.add(n_items * 4);
-    w.itj0 = L.add(n_items * 4);
-    w.itnj = L.add(n_items * 4);
-    w.itown = L.add(n_items * 4);
     w.idesc = L.add(n_items * sizeof(ItemDesc));
     w.updesc = L.add(std::max<size_t>(1, c->upd_wg_c0.size()) * sizeof(UpdDesc));
     const int64_t n_pblk = (N + 255) / 256;
@@ -467,14 +461,8 @@ void plan_layout(pdg_ctx *c) {
     w.dsrc = L.add(std::max<int64_t>(1, N) * sizeof(ZSrc));
     w.bcsrc = L.add(std::max<int64_t>(1, n_pblk * kPupdateKmax * std::max(pc.nq0, 1)) * sizeof(ZSrc));
     w.rtit0 = L.add((n_rt + 1) * 4);
-    w.dofrt = L.add(N * 4);
     w.itdot = L.add(n_items * 8);  // one share per Schwarz workgroup (at most one per item)
     w.rowpart = L.add(n_items * kTile * 8);
-    w.sysn = L.add(n_dsys * 4);
-    w.sysnt = L.add(n_dsys * 4);
-    w.systoff = L.add(n_dsys * 8);
-    w.sysdof0 = L.add(n_dsys * 8);
-    w.syscb = L.add(n_dsys * 8);
     w.rtk = L.add(n_rt * 4);
     w.rtnt = L.add(n_rt * 4);
     w.rtcb = L.add(n_rt * 8);
@@ -487,8 +475,6 @@ void plan_layout(pdg_ctx *c) {
             if (pc.fallback[s]) fb_tiles += pc.sys[s].nt * (pc.sys[s].nt + 1) / 2;
     w.tfb = L.add(fb_tiles * kTile * kTile * 4);
     w.dsc = L.add(pc.dscale.size() * 4);
-    w.rbase = L.add(n_dsys * 8);
-    w.sysf32 = L.add(n_dsys * 4);
     w.P = L.add(pc.P.size() * 8);
     w.ecoa = L.add(pc.elem_coarse.size() * 4);
     w.elsys = L.add(n * 4);
@@ -501,9 +487,7 @@ void plan_layout(pdg_ctx *c) {
     w.rupd = L.add((n_sys + 1) * 4);
     w.ritem = L.add((n_sys + 1) * 4);
     w.rowner = L.add(n_sys * 4);
-    w.spwg = L.add(c->spmv_wg_g0.size() * 4);
     w.spdesc = L.add(std::max<size_t>(1, c->spmv_wg_g0.size()) * sizeof(SpDesc));
-    w.upwg = L.add(c->upd_wg_c0.size() * 4);
     w.chunk0 = L.add(n_sys * 4);
     w.x = L.add(N * 8);
     w.r = L.add(N * 8);
@@ -519,7 +503,6 @@ void plan_layout(pdg_ctx *c) {
     w.part = L.add(std::max<int64_t>(1, (int64_t)c->spmv_wg_g0.size()) * 2 * 8);  // SpMV partials
     w.rrpart = L.add(std::max<int64_t>(1, (int64_t)c->upd_wg_c0.size()) * 8);     // update partials
     w.lanc = L.add((size_t)n_sys * c->lcap * 16);                                 // PCG coefficients
-    w.pucr = L.add(((N + 255) / 256) * 2 * 4);  // coarse range of every p-update block
     w.cbase = L.add(std::max(pc.n_coarse, 1) * 4);   // coarse values: tile-row position of each coarse element
 }
 
@@ -626,11 +609,6 @@ void upload_items(pdg_ctx *c) {
         upload(c, c->w.pblk, bl);
         upload(c, c->w.bcsrc, cs);
     }
-    upload(c, c->w.itsys, c->it_sys);
-    upload(c, c->w.itrow, c->it_row);
-    upload(c, c->w.itj0, c->it_j0);
-    upload(c, c->w.itnj, c->it_nj);
-    upload(c, c->w.itown, c->it_own);
     upload(c, c->w.rtit0, c->rt_item0);
     upload(c, c->w.ritem, c->r_item);
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -663,19 +641,9 @@ SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) 
     a.nd = c->mesh.nd;
     a.n_sub = c->pc.n_sub;
     a.nq0 = c->pc.q > 0 ? c->pc.nq0 : 0;
-    a.item_sys = wptr<int32_t>(c, c->w.itsys);
-    a.item_row = wptr<int32_t>(c, c->w.itrow);
-    a.item_j0 = wptr<int32_t>(c, c->w.itj0);
-    a.item_nj = wptr<int32_t>(c, c->w.itnj);
-    a.item_owner = wptr<int32_t>(c, c->w.itown);
     a.part = wptr<double>(c, c->w.rowpart);
     a.itemdot = wptr<double>(c, c->w.itdot);
     a.colpart = wptr<double>(c, c->w.colp);
-    a.sys_n = wptr<int32_t>(c, c->w.sysn);
-    a.sys_nt = wptr<int32_t>(c, c->w.sysnt);
-    a.sys_toff = wptr<int64_t>(c, c->w.systoff);
-    a.sys_dof0 = wptr<int64_t>(c, c->w.sysdof0);
-    a.sys_cbase = wptr<int64_t>(c, c->w.syscb);
     a.csys_ce0 = wptr<int32_t>(c, c->w.csys0);
     a.tiles_local = wptr<void>(c, c->w.tloc);
     a.tiles_coarse = wptr<void>(c, c->w.tcoa);
@@ -689,8 +657,6 @@ SchwarzArgs schwarz_args(pdg_ctx *c, int mode, const double *r, DevScalars *sc) 
     a.n_sys_one = c->n_sys == 1 ? 1 : 0;
     if (c->pc.local_prec == PDG_BF16) {
         a.dscale = wptr<float>(c, c->w.dsc);
-        a.sys_rbase = wptr<int64_t>(c, c->w.rbase);
-        a.sys_f32 = wptr<int32_t>(c, c->w.sysf32);
         a.tiles_fallback = wptr<char>(c, c->w.tfb);
     }
     return a;
@@ -751,8 +717,6 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
     u.nq0 = c->pc.q > 0 && !c->no_precond ? c->pc.nq0 : 0;
     u.grp_ptr = wptr<int32_t>(c, c->w.grpptr);
     u.grp_elems = wptr<int32_t>(c, c->w.grpel);
-    u.grp_sys = wptr<int32_t>(c, c->w.upsys);
-    u.wg_c0 = wptr<int32_t>(c, c->w.upwg);
     u.n_wg = (int)c->upd_wg_c0.size() - 1;
     u.x = x;
     u.r = r;
@@ -781,10 +745,8 @@ PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, const double *r, Dev
     p.n_elem = c->mesh.n_elem;
     p.P = p.nq0 > 0 ? wptr<double>(c, c->w.P) : nullptr;
     p.elem_coarse = p.nq0 > 0 ? wptr<int32_t>(c, c->w.ecoa) : nullptr;
-    p.blk_crange = wptr<int32_t>(c, c->w.pucr);
     p.coarse_base = wptr<int32_t>(c, c->w.cbase);
     p.elem_sys = wptr<int32_t>(c, c->w.elsys);
-    p.dof_rt = wptr<int32_t>(c, c->w.dofrt);
     p.rt_item0 = wptr<int32_t>(c, c->w.rtit0);
     p.rt_k = wptr<int32_t>(c, c->w.rtk);
     p.rt_nt = wptr<int32_t>(c, c->w.rtnt);
@@ -1352,7 +1314,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.gslot, c->grp_slot_off);
         upload(c, w.gcol, c->grp_col);
         upload(c, w.gval, c->grp_val);
-        upload(c, w.gsys, c->grp_sys);
         upload(c, w.mass, c->M);
         upload(c, w.minv, c->Minv);
         upload(c, w.qpptr, m.qp_ptr);
@@ -1364,7 +1325,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.prm, prm);
         upload(c, w.subptr, pc.sub_ptr);
         upload(c, w.subel, pc.sub_elems);
-        upload(c, w.dofrt, c->dof_rt);
         upload(c, w.rtk, c->rt_k);
         upload(c, w.rtnt, c->rt_nt);
         upload(c, w.rtcb, c->rt_cbase);
@@ -1372,7 +1332,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         upload(c, w.rspmv, c->r_spmv);
         upload(c, w.rupd, c->r_upd);
         upload(c, w.rowner, c->r_owner);
-        upload(c, w.spwg, c->spmv_wg_g0);
         {
             std::vector<SpDesc> sd(c->spmv_wg_g0.size() - 1);
             for (size_t k = 0; k < sd.size(); ++k) {
@@ -1385,10 +1344,9 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
             }
             upload(c, w.spdesc, sd);
         }
-        upload(c, w.upwg, c->upd_wg_c0);
         upload(c, w.chunk0, std::vector<int32_t>(c->r_chunk.begin(), c->r_chunk.end() - 1));
         upload(c, w.elsys, c->elem_sys);
-        std::vector<int32_t> sys_n, sys_nt;
+        std::vector<int32_t> sys_n;
         std::vector<int64_t> sys_toff, sys_cb;
         int64_t nloc_tiles = 0;
         for (int sidx = 0; sidx < pc.n_sub; ++sidx) nloc_tiles += pc.sys[sidx].nt * (pc.sys[sidx].nt + 1) / 2;
@@ -1407,7 +1365,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
             }
         for (size_t sidx = 0; sidx < pc.sys.size(); ++sidx) {
             sys_n.push_back((int32_t)pc.sys[sidx].n);
-            sys_nt.push_back((int32_t)pc.sys[sidx].nt);
             // local systems index the local store (or the fallback store),
             // coarse systems the coarse store
             sys_toff.push_back(fb_off[sidx] >= 0 ? fb_off[sidx]
@@ -1415,13 +1372,7 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
                                                       : pc.sys[sidx].tile_off - nloc_tiles);
             sys_cb.push_back(pc.sys[sidx].tile_off);
         }
-        upload(c, w.rbase, rbase);
-        upload(c, w.sysf32, sys_f32);
         if (loc_b16) upload(c, w.dsc, pc.dscale);
-        upload(c, w.sysn, sys_n);
-        upload(c, w.sysnt, sys_nt);
-        upload(c, w.systoff, sys_toff);
-        upload(c, w.syscb, sys_cb);
         // the item descriptors hold these in 32 bits
         const int64_t lim = (int64_t)1 << 31;
         if (pc.n_tiles >= lim || m.n_elem * nd >= lim) throw Error(PDG_EINVAL, "problem too large for 32-bit tile or dof indices");
@@ -1438,7 +1389,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
             for (int k = a0 + 1; k < a1 && contiguous; ++k) contiguous = pc.sub_elems[k] == pc.sub_elems[k - 1] + 1;
             if (contiguous) sys_dof0[sidx] = (int64_t)pc.sub_elems[a0] * nd;
         }
-        upload(c, w.sysdof0, sys_dof0);
         c->ds_dof0 = sys_dof0;
         // tiles, converted to the storage precision
         const int64_t nloc = nloc_tiles * kTile * kTile;
@@ -1483,7 +1433,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         put_tiles(w.tcoa, pc.inv64.data() + nloc, ncoa, pc.coarse_prec);
         upload(c, w.P, pc.P);
         upload(c, w.ecoa, pc.elem_coarse);
-        upload(c, w.pucr, pupdate_coarse_ranges(c));
         upload(c, w.cbase, coarse_value_base(c));
         upload(c, w.grpptr, c->grp_ptr);
         upload(c, w.grpel, c->grp_elems);
@@ -1524,8 +1473,6 @@ pdg_status pdg_bind_workspace(pdg_ctx *c, void *dev_ptr, size_t bytes) {
         c->dA.grp_col = wptr<int32_t>(c, w.gcol);
         c->dA.grp_val = wptr<double>(c, w.gval);
         c->dA.mass = wptr<double>(c, w.mass);
-        c->dA.grp_sys = wptr<int32_t>(c, w.gsys);
-        c->dA.wg_g0 = wptr<int32_t>(c, w.spwg);
         c->dA.n_wg = (int)c->spmv_wg_g0.size() - 1;
         c->dA.wg_desc = wptr<SpDesc>(c, w.spdesc);
         c->dA.one_sys = c->n_sys == 1 ? 1 : 0;

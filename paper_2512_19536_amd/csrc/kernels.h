@@ -75,8 +75,6 @@ struct DevMatrix {
     const int32_t *grp_col;      // [slots*G]
     const double *grp_val;       // [slots*G*nd*nd]
     const double *mass;          // [n_rows][nd][nd]
-    const int32_t *grp_sys;      // [n_groups] system of each group
-    const int32_t *wg_g0;        // [n_wg+1] groups of each workgroup (contiguous, one system)
     int n_wg;
     const SpDesc *wg_desc;       // [n_wg]
     int one_sys;                 // 1: one system (its stop flag is sc[0])
@@ -111,8 +109,6 @@ struct UpdateArgs {
     int pre_pq;             // 1: take (p, q) from sc.pq_sum instead of summing the SpMV partials
     int nd, nq0;
     const int32_t *grp_ptr, *grp_elems;  // update chunks: element runs inside one coarse element
-    const int32_t *grp_sys;              // system of each chunk
-    const int32_t *wg_c0;                // [n_wg+1] chunks of each workgroup (contiguous, one system)
     int n_wg;
     double *x, *r;
     const double *p, *q;
@@ -149,14 +145,9 @@ struct alignas(64) ItemDesc {
 struct SchwarzArgs {
     int mode;               // 0 apply only, 1/2 inside PCG (also writes the (r, z) shares)
     int nd, n_sub, nq0;
-    const int32_t *item_sys, *item_row, *item_j0, *item_nj, *item_owner;
     double *part;                // [n_items][64] row partials
     double *colpart;             // [n_tiles_total][64] column partials (indexed by global tile index)
     double *itemdot;             // [n_items] shares of (r, z) + (r0, z0)
-    const int32_t *sys_n, *sys_nt;
-    const int64_t *sys_toff;     // tile offset of each dense system inside its own store
-    const int64_t *sys_cbase;    // global tile index of each dense system's first tile
-    const int64_t *sys_dof0;     // first dof of a subdomain whose elements are one contiguous run, else -1
     const int32_t *csys_ce0;     // [n_sys+1] first coarse element of each batch system
     const void *tiles_local;     // tile store of the local systems
     const void *tiles_coarse;    // tile store of the coarse systems
@@ -168,12 +159,11 @@ struct SchwarzArgs {
     const ItemDesc *item_desc;   // [n_items]
     int n_sys_one;               // 1: one system in the context (its stop flag is sc[0])
     // BF16 local store only (else null): the stored tiles of local system s
-    // hold C = D^{-1} K_s^{-1} D^{-1}; d of its row i is dscale[sys_rbase[s] + i].
-    // Systems with sys_f32[s] = 1 are stored in FP32 in tiles_fallback instead
-    // (sys_toff then indexes that store), unscaled.
+    // hold C = D^{-1} K_s^{-1} D^{-1}; d of its row i is dscale[rbase + i] (rbase
+    // and the FP32-fallback flag are in the item descriptor).  Systems flagged
+    // FP32 are stored unscaled in tiles_fallback (their descriptor's tile
+    // offset indexes that store).
     const float *dscale;
-    const int64_t *sys_rbase;
-    const int32_t *sys_f32;
     const void *tiles_fallback;
 };
 
@@ -208,10 +198,7 @@ struct PupdateArgs {
     int64_t n_elem;
     const double *P;
     const int32_t *elem_coarse;  // coarse element of each element (system-contiguous numbering)
-    const int32_t *blk_crange;   // [blocks][2]: first coarse element of the block's dofs and their
-                                 // count, or kPupdateKmax + 1 (coarse values read per dof)
     const int32_t *elem_sys;     // batch system of each element
-    const int32_t *dof_rt;       // [N] tile row * 64 + row inside the tile, of every fine dof
     const int32_t *rt_item0;     // [n_rt+1] first item of each tile row
     const int32_t *rt_k, *rt_nt; // tile-row index inside its dense system, tile rows of the system
     const int64_t *rt_cbase;     // global tile index of the dense system's first tile
