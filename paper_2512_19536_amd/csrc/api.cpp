@@ -79,6 +79,7 @@ struct pdg_ctx {
     // options
     int true_resid = 0, chunk = 4, timing = 0, item_kb = 128, use_graph = 0, spmv_wpg = 4;
     int coarse_split = 3;        // coarse-system items are cut to 1/coarse_split of the item size
+                                 // (set at preconditioner setup, changed by the autotuner)
     int prev_iters = 0;
     // host data
     Mesh mesh;
@@ -359,6 +360,22 @@ int64_t max_tiles_per_item(const pdg_ctx *c) {
     int64_t nj = 1;
     while (schwarz_lds_bytes(ls, cs, (int)nj + 1) <= kSchwarzLdsMax) ++nj;
     return nj;
+}
+
+// Coarse items are cut smaller only where the coarse tiles are a small share
+// (at most an eighth) of the apply's bytes: there they would otherwise form
+// the grid's tail.  Where the coarse system dominates, small items would only
+// add per-item latency.
+int default_coarse_split(const pdg_ctx *c) {
+    const Precond &pc = c->pc;
+    double coarse = 0.0, all = 0.0;
+    for (size_t s = 0; s < pc.sys.size(); ++s) {
+        const double nt = (double)pc.sys[s].nt;
+        const double b = nt * (nt + 1.0) / 2.0 * tile_elem_bytes(sys_prec(pc, s));
+        all += b;
+        if ((int)s >= pc.n_sub) coarse += b;
+    }
+    return coarse * 8.0 <= all ? 3 : 1;
 }
 
 int64_t plan_items(pdg_ctx *c, int kb, bool count_only) {
@@ -1198,6 +1215,7 @@ pdg_status pdg_setup_preconditioner(pdg_ctx *c, const pdg_precond_desc *d) {
                       std::ldexp(1.0, -c->bf16_margin_log2));
         build_group_ell(c);
         plan_chunks(c);
+        c->coarse_split = default_coarse_split(c);
         plan_items(c, c->item_kb, false);
         // room for the finest split the autotuner tries (64 KiB items, coarse items cut in four)
         const int cs = c->coarse_split;

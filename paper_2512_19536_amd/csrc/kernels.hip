@@ -61,22 +61,38 @@ __device__ inline void block_sum(double (&v)[NV], double (&tot)[NV]) {
     __syncthreads();
 }
 
+// This thread's share of the sum of part[k * stride + slot], k < n: the
+// entries k = threadIdx.x + m * BS, loaded 16 per round (those past n read
+// nothing) so that one memory round trip covers up to 16 * BS partials, and
+// added into four running sums in a fixed order.
+template <int BS>
+__device__ inline double thread_sum_partials(const double *part, int n, int stride, int slot) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = threadIdx.x; k0 < n; k0 += 16 * BS) {
+        double w[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int k = k0 + u * BS;
+            w[u] = k < n ? part[(int64_t)k * stride + slot] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[u & 3] += w[u];
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Block total of one value per thread, in every thread.
+template <int BS>
+__device__ inline double block_total(double v) {
+    double w[1] = {v}, t[1];
+    block_sum<1, BS>(w, t);
+    return t[0];
+}
+
 // Sum of part[k * stride + slot], k < n, in a fixed order, in every thread.
-// Four independent running sums per thread keep four loads in flight.
 template <int BS>
 __device__ inline double block_sum_partials(const double *part, int n, int stride, int slot) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int k = threadIdx.x;
-    for (; k + 3 * BS < n; k += 4 * BS) {
-        a0 += part[(int64_t)k * stride + slot];
-        a1 += part[(int64_t)(k + BS) * stride + slot];
-        a2 += part[(int64_t)(k + 2 * BS) * stride + slot];
-        a3 += part[(int64_t)(k + 3 * BS) * stride + slot];
-    }
-    for (; k < n; k += BS) a0 += part[(int64_t)k * stride + slot];
-    double v[1] = {(a0 + a1) + (a2 + a3)}, t[1];
-    block_sum<1, BS>(v, t);
-    return t[0];
+    return block_total<BS>(thread_sum_partials<BS>(part, n, stride, slot));
 }
 
 __device__ inline bool finite(double x) { return __builtin_isfinite(x); }
@@ -338,15 +354,21 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
 #pragma unroll
             for (int j = 0; j < NQ; ++j) f_P[j] = a.P[f_idx * NQ + j];
     }
+    // The stop flag, the scalars and this thread's share of the (p, q)
+    // partials are requested together with the dof above, before the first
+    // barrier.
+    const int done = threadIdx.x == 0 ? sc->done : 0;
+    const int iters = sc->iters;
+    const double rz_even = sc->rz[0], rz_odd = sc->rz[1];
+    const double pq_t =
+        (a.init || a.pre_pq) ? 0.0 : thread_sum_partials<128>(a.pqpart + 2 * (int64_t)dsc.g0, dsc.g1 - dsc.g0, 2, 0);
     // the owner workgroup may set `done` during this launch
-    if (block_bcast<128>(threadIdx.x == 0 ? sc->done : 0)) return;
+    if (block_bcast<128>(done)) return;
     double alpha = 0.0;
     if (!a.init) {
-        const int g0 = dsc.g0;
-        const double pq = a.pre_pq ? sc->pq_sum
-                                   : block_sum_partials<128>(a.pqpart + 2 * (int64_t)g0, dsc.g1 - g0, 2, 0);
-        const int j = sc->iters + 1;
-        alpha = sc->rz[(j - 1) & 1] / pq;
+        const double pq = a.pre_pq ? sc->pq_sum : block_total<128>(pq_t);
+        const int j = iters + 1;
+        alpha = ((j - 1) & 1 ? rz_odd : rz_even) / pq;
         if (wg == a.rng.upd[b] && threadIdx.x == 0) {
             sc->pq = pq;
             sc->alpha = alpha;
@@ -790,26 +812,48 @@ __device__ inline TileRow tile_row(const ZSrc &z) {
     return TileRow{z.it0, z.it0 + (z.nl >> 8), z.knt >> 16, z.knt & 0xffff, (int64_t)z.cb};
 }
 
-__device__ inline double tile_row_value(const PupdateArgs &a, const TileRow &t, int lane) {
-    double v = 0.0;
-    for (int it = t.it0; it < t.it1; ++it) v += a.part[(int64_t)it * TILE + lane];
-    // column partials of the stored tiles (I, K), I > K, below this tile row:
-    // 16 loads per round (those past the last tile row read nothing) into
-    // eight partial sums, added in a fixed order
+// Entry `lane` of tile row t of z is the sum of the row partials of the tile
+// row's items and of the column partials of the stored tiles (I, K), I > K,
+// below it.  The first round requests up to 4 item and 16 column partials at
+// once (those past the end read nothing); tile_row_rest waits for them, reads
+// any further ones (16 per round) and adds all in a fixed order.
+constexpr int kTrFirst = 20;
+
+__device__ inline void tile_row_first(const PupdateArgs &a, const TileRow &t, int lane, double (&w)[kTrFirst]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = t.it0 + u < t.it1 ? a.part[(int64_t)(t.it0 + u) * TILE + lane] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int I = t.K + 1 + u;
+        w[4 + u] = I < t.nt ? a.colpart[(t.cb + (int64_t)I * (I + 1) / 2 + t.K) * TILE + lane] : 0.0;
+    }
+}
+
+__device__ inline double tile_row_rest(const PupdateArgs &a, const TileRow &t, int lane, const double (&w)[kTrFirst]) {
+    double v = (w[0] + w[1]) + (w[2] + w[3]);
+    for (int it = t.it0 + 4; it < t.it1; ++it) v += a.part[(int64_t)it * TILE + lane];
     const int K = t.K, nt = t.nt;
     const int64_t cb = t.cb;
-    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int I0 = K + 1; I0 < nt; I0 += 16) {
-        double w[16];
+    double c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = w[4 + u] + w[12 + u];
+    for (int I0 = K + 17; I0 < nt; I0 += 16) {
+        double x[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int I = I0 + u;
-            w[u] = I < nt ? a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane] : 0.0;
+            x[u] = I < nt ? a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) c[u & 7] += w[u];
+        for (int u = 0; u < 16; ++u) c[u & 7] += x[u];
     }
     return v + (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+}
+
+__device__ inline double tile_row_value(const PupdateArgs &a, const TileRow &t, int lane) {
+    double w[kTrFirst];
+    tile_row_first(a, t, lane, w);
+    return tile_row_rest(a, t, lane, w);
 }
 
 __device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) {
@@ -822,18 +866,19 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const int64_t n = a.n_elem * nd;
     const int64_t i0 = (int64_t)blockIdx.x * 256;
     const int64_t idx = i0 + threadIdx.x;
-    // the block's record, and each dof's source record, are read at once
+    // The block's record, then everything that depends on it alone at once:
+    // this dof's old direction and the record of where its value of z is,
+    // the coarse rows the block keeps, the first system's stop flag.  z = B r
+    // depends only on the Schwarz partials, not on this launch's reductions,
+    // so it is formed first (for every dof of the block, also of systems
+    // that turn out to be done; those values are dropped).
     const PuBlk bk = a.blk[blockIdx.x];
     const int my = idx < n ? (bk.s_lo == bk.s_hi ? bk.s_lo : a.elem_sys[idx / nd]) : -1;
-    // z = B r depends only on the Schwarz partials, not on this launch's
-    // reductions, so it is formed first (for every dof of the block, also of
-    // systems that turn out to be done; those values are dropped) and its
-    // memory latency does not add to that of the reductions below.
     const double p_old = (my >= 0 && a.mode == 2) ? a.p[idx] : 0.0;
-    // where this dof's fine value is (static tables, read before the coarse part's barrier)
+    const bool fine = my >= 0 && !a.r_ident;
     int f_lane = 0;
     TileRow f_tr{0, 0, 0, 0, 0};
-    if (my >= 0 && !a.r_ident) {
+    if (fine) {
         const ZSrc zs = a.dof_src[idx];
         f_lane = zs.nl & 63;
         f_tr = tile_row(zs);
@@ -843,40 +888,55 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     // contiguously), so the block computes their n_c * NQ values into LDS
     // (the range is planned on the host)
     constexpr int KMAX = kPupdateKmax;
-    __shared__ double s_z0[KMAX * (NQ > 0 ? NQ : 1)];
+    constexpr int NV = NQ > 0 ? NQ : 1;
+    __shared__ double s_z0[KMAX * NV];
     int c_lo = 0, n_c = KMAX + 1;
     if (NQ > 0) {
         c_lo = bk.c_lo;
         n_c = bk.n_c;
-        if (n_c <= KMAX) {
-            for (int t = threadIdx.x; t < n_c * NQ; t += 256) {
-                const ZSrc zs = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NQ) + t];
-                s_z0[t] = tile_row_value(a, tile_row(zs), zs.nl & 63);
-            }
-            __syncthreads();
-        }
     }
+    const bool c_val = NQ > 0 && n_c <= KMAX && (int)threadIdx.x < n_c * NQ;
+    int c_lane = 0;
+    TileRow c_tr{0, 0, 0, 0, 0};
+    if (c_val) {
+        const ZSrc zs = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NV) + threadIdx.x];
+        c_lane = zs.nl & 63;
+        c_tr = tile_row(zs);
+    }
+    const int done_lo = (a.mode != 0 && threadIdx.x == 0) ? a.sc[bk.s_lo].done : 0;
+    // the partials of the fine and the coarse value, requested together
+    double wf[kTrFirst], wc[kTrFirst];
+    if (fine) tile_row_first(a, f_tr, f_lane, wf);
+    if (c_val) tile_row_first(a, c_tr, c_lane, wc);
+    // this thread's share of the first system's (r, z) partials
+    double rz_t = 0.0;
+    if (a.mode != 0 && !a.pre_rz)
+        rz_t = a.r_ident ? thread_sum_partials<256>(a.rrpart + bk.u0, bk.u1 - bk.u0, 1, 0)
+                         : thread_sum_partials<256>(a.itemdot + bk.it0, bk.it1 - bk.it0, 1, 0);
     double zz = 0.0;
-    if (my >= 0) {
-        if (a.r_ident) {
-            zz = a.r_ident[idx];
-        } else {
-            zz = tile_row_value(a, f_tr, f_lane);
+    if (my >= 0) zz = a.r_ident ? a.r_ident[idx] : tile_row_rest(a, f_tr, f_lane, wf);
+    if (NQ > 0 && n_c <= KMAX) {
+        if (c_val) s_z0[threadIdx.x] = tile_row_rest(a, c_tr, c_lane, wc);
+        // more than 256 kept values (NQ = 35): the rest one by one
+        for (int t = threadIdx.x + 256; t < n_c * NQ; t += 256) {
+            const ZSrc zs = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NV) + t];
+            s_z0[t] = tile_row_value(a, tile_row(zs), zs.nl & 63);
         }
-        if (NQ > 0) {
-            const int64_t e = idx / nd;
-            const int ce = a.elem_coarse[e];
-            const double *Pr = a.P + idx * NQ;
-            if (n_c <= KMAX) {
+        __syncthreads();
+    }
+    if (NQ > 0 && my >= 0) {
+        const int64_t e = idx / nd;
+        const int ce = a.elem_coarse[e];
+        const double *Pr = a.P + idx * NQ;
+        if (n_c <= KMAX) {
 #pragma unroll
-                for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
-            } else {
-                const int g0 = a.coarse_base[ce];
+            for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
+        } else {
+            const int g0 = a.coarse_base[ce];
 #pragma unroll
-                for (int j = 0; j < NQ; ++j) {
-                    const int gi = g0 + j;
-                    zz = fma(Pr[j], tile_row_value(a, gi >> 6, gi & 63), zz);
-                }
+            for (int j = 0; j < NQ; ++j) {
+                const int gi = g0 + j;
+                zz = fma(Pr[j], tile_row_value(a, gi >> 6, gi & 63), zz);
             }
         }
     }
@@ -887,14 +947,16 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
         const int s_lo = bk.s_lo, s_hi = bk.s_hi;
         for (int b = s_lo; b <= s_hi; ++b) {
             DevScalars *sc = a.sc + b;
-            // the owner block may set `done` during this launch
-            if (block_bcast<256>(threadIdx.x == 0 ? sc->done : 0)) continue;
             const bool first = b == s_lo;
+            // the owner block may set `done` during this launch
+            if (block_bcast<256>(first ? done_lo : (threadIdx.x == 0 ? sc->done : 0))) continue;
             const int it0 = a.r_ident ? (first ? bk.u0 : a.rng.upd[b]) : (first ? bk.it0 : a.rng.item[b]);
             const int it1 = a.r_ident ? (first ? bk.u1 : a.rng.upd[b + 1]) : (first ? bk.it1 : a.rng.item[b + 1]);
-            const double rz = a.pre_rz ? sc->rz_sum
-                                       : block_sum_partials<256>(a.r_ident ? a.rrpart + it0 : a.itemdot + it0,
-                                                                 it1 - it0, 1, 0);
+            const double rz =
+                a.pre_rz ? sc->rz_sum
+                         : block_total<256>(first ? rz_t
+                                                  : thread_sum_partials<256>(a.r_ident ? a.rrpart + it0 : a.itemdot + it0,
+                                                                             it1 - it0, 1, 0));
             const int j = a.mode == 2 ? sc->jcur : 0;
             const double bt = a.mode == 2 ? rz / sc->rz[(j - 1) & 1] : 0.0;
             if (my == b) {
