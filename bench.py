@@ -45,8 +45,12 @@ def log(*a):
 
 
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2512_19536_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the kernel source and its header (kernels.hip, kernels.h)."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2512_19536_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(workload_tag, n_launch_bytes):

@@ -872,23 +872,26 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     // depends only on the Schwarz partials, not on this launch's reductions,
     // so it is formed first (for every dof of the block, also of systems
     // that turn out to be done; those values are dropped).
+    // The records that do not depend on the block's record are requested with it:
+    // this dof's source record and old direction, and the source record of the
+    // coarse value this thread may keep (the slots past the block's n_c * NQ
+    // values exist and are not used).
+    constexpr int KMAX = kPupdateKmax;
+    constexpr int NV = NQ > 0 ? NQ : 1;
+    const bool in = idx < n;
     const PuBlk bk = a.blk[blockIdx.x];
-    const int my = idx < n ? (bk.s_lo == bk.s_hi ? bk.s_lo : a.elem_sys[idx / nd]) : -1;
-    const double p_old = (my >= 0 && a.mode == 2) ? a.p[idx] : 0.0;
+    ZSrc zf{0, 0, 0, 0}, zc{0, 0, 0, 0};
+    if (in && !a.r_ident) zf = a.dof_src[idx];
+    const double p_old = (in && a.mode == 2) ? a.p[idx] : 0.0;
+    if (NQ > 0 && (int)threadIdx.x < KMAX * NV) zc = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NV) + threadIdx.x];
+    const int my = in ? (bk.s_lo == bk.s_hi ? bk.s_lo : a.elem_sys[idx / nd]) : -1;
     const bool fine = my >= 0 && !a.r_ident;
-    int f_lane = 0;
-    TileRow f_tr{0, 0, 0, 0, 0};
-    if (fine) {
-        const ZSrc zs = a.dof_src[idx];
-        f_lane = zs.nl & 63;
-        f_tr = tile_row(zs);
-    }
+    const int f_lane = zf.nl & 63;
+    const TileRow f_tr = tile_row(zf);
     // coarse values z0 of the block's coarse elements, once per block: the
     // block's elements usually lie in one or two coarse elements (numbered
     // contiguously), so the block computes their n_c * NQ values into LDS
     // (the range is planned on the host)
-    constexpr int KMAX = kPupdateKmax;
-    constexpr int NV = NQ > 0 ? NQ : 1;
     __shared__ double s_z0[KMAX * NV];
     int c_lo = 0, n_c = KMAX + 1;
     if (NQ > 0) {
@@ -896,13 +899,8 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
         n_c = bk.n_c;
     }
     const bool c_val = NQ > 0 && n_c <= KMAX && (int)threadIdx.x < n_c * NQ;
-    int c_lane = 0;
-    TileRow c_tr{0, 0, 0, 0, 0};
-    if (c_val) {
-        const ZSrc zs = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NV) + threadIdx.x];
-        c_lane = zs.nl & 63;
-        c_tr = tile_row(zs);
-    }
+    const int c_lane = zc.nl & 63;
+    const TileRow c_tr = tile_row(zc);
     const int done_lo = (a.mode != 0 && threadIdx.x == 0) ? a.sc[bk.s_lo].done : 0;
     // the partials of the fine and the coarse value, requested together
     double wf[kTrFirst], wc[kTrFirst];
@@ -1143,8 +1141,10 @@ __device__ inline double xexp(double x) {
     return fabs(x) < 1e-4 ? 1.0 + x * 0.5 + x * x / 12.0 : x / (1.0 - exp(-x));
 }
 
-__device__ inline void ionic_model(double V, const double *y, const double *prm, double &f, double *dy,
-                                   int &bad) {
+// vcl: the chloride reversal potential prm[17] log(prm[15] / prm[16]) (a
+// constant of the parameter set).
+__device__ inline void ionic_model(double V, const double *y, const double *prm, double vcl, double &f,
+                                   double *dy, int &bad) {
     const double n = y[0], h = y[1], ko = y[2], nai = y[3], cai = y[4];
     const double ki = prm[21] + (prm[22] - nai);
     const double nao = prm[23] - prm[10] * (nai - prm[22]);
@@ -1157,7 +1157,6 @@ __device__ inline void ionic_model(double V, const double *y, const double *prm,
     }
     const double vna = prm[17] * log(nao / nai);
     const double vk = prm[17] * log(ko / ki);
-    const double vcl = prm[17] * log(prm[15] / prm[16]);
     const double am = xexp(0.1 * (V + 30.0));
     const double bm = 4.0 * exp(-(V + 55.0) / 18.0);
     const double an = 0.1 * xexp(0.1 * (V + 34.0));
@@ -1222,7 +1221,11 @@ struct NB { static constexpr int v = DIM == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) 
 // u~ = ext_now u^k + ext_prev u^(k-1) (2, -1: to t^(k+1); 3/2, -1/2: to the
 // Crank-Nicolson mid-point).
 template <int DIM, int P>
-__global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
+struct IonicMinWaves { static constexpr int value = NB<DIM, P>::v <= 10 ? 3 : 1; };
+
+template <int DIM, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(IonicMinWaves<DIM, P>::value)))
+void k_ionic(IonicArgs a) {
     constexpr int ND = NB<DIM, P>::v;
     const int64_t e = blockIdx.x;
     const int lane = threadIdx.x;
@@ -1244,6 +1247,7 @@ __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
         s_y[l][i] = a.y[((int64_t)l * n + e) * ND + i];
     }
     __syncthreads();
+    const double vcl = a.prm[17] * log(a.prm[15] / a.prm[16]);
     const int64_t q0 = a.qp_ptr[e], q1 = a.qp_ptr[e + 1];
     constexpr int NOUT = (5 * ND + 63) / 64;
     double accG[NOUT];
@@ -1265,13 +1269,14 @@ __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
 #pragma unroll
                 for (int l = 0; l < 5; ++l) yv[l] = fma(phi[k], s_y[l][k], yv[l]);
             }
+            // phi is stored before the model is evaluated, so its registers are free there
+#pragma unroll
+            for (int k = 0; k < ND; ++k) s_phi[lane][k] = phi[k];
             double f, dy[5];
-            ionic_model(u, yv, s_prm, f, dy, bad);
+            ionic_model(u, yv, s_prm, vcl, f, dy, bad);
             const double w = a.qp_w[q];
 #pragma unroll
             for (int l = 0; l < 5; ++l) s_w[lane][l] = w * dy[l];
-#pragma unroll
-            for (int k = 0; k < ND; ++k) s_phi[lane][k] = phi[k];
         } else {
 #pragma unroll
             for (int l = 0; l < 5; ++l) s_w[lane][l] = 0.0;
@@ -1279,13 +1284,15 @@ __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
             for (int k = 0; k < ND; ++k) s_phi[lane][k] = 0.0;
         }
         __syncthreads();
+        // the chunk's points (the slots past the last one hold zeros)
+        const int nqc = (int)(q1 - c0 < 64 ? q1 - c0 : 64);
 #pragma unroll
         for (int t = 0; t < NOUT; ++t) {
             const int o = lane + 64 * t;
             if (o < 5 * ND) {
                 const int l = o / ND, k = o - l * ND;
                 double s = accG[t];
-                for (int qq = 0; qq < 64; ++qq) s = fma(s_w[qq][l], s_phi[qq][k], s);
+                for (int qq = 0; qq < nqc; ++qq) s = fma(s_w[qq][l], s_phi[qq][k], s);
                 accG[t] = s;
             }
         }
@@ -1338,19 +1345,20 @@ __global__ __launch_bounds__(64) void k_ionic(IonicArgs a) {
 #pragma unroll
                 for (int l = 0; l < 5; ++l) yv[l] = fma(phi[k], s_y[l][k], yv[l]);
             }
-            double f;
-            ionic_model(a.ext_now * u + a.ext_prev * up, yv, s_prm, f, nullptr, bad);
-            s_w[lane][0] = a.qp_w[q] * f;
 #pragma unroll
             for (int k = 0; k < ND; ++k) s_phi[lane][k] = phi[k];
+            double f;
+            ionic_model(a.ext_now * u + a.ext_prev * up, yv, s_prm, vcl, f, nullptr, bad);
+            s_w[lane][0] = a.qp_w[q] * f;
         } else {
             s_w[lane][0] = 0.0;
 #pragma unroll
             for (int k = 0; k < ND; ++k) s_phi[lane][k] = 0.0;
         }
         __syncthreads();
+        const int nqc = (int)(q1 - c0 < 64 ? q1 - c0 : 64);
         if (lane < ND)
-            for (int qq = 0; qq < 64; ++qq) accI = fma(s_w[qq][0], s_phi[qq][lane], accI);
+            for (int qq = 0; qq < nqc; ++qq) accI = fma(s_w[qq][0], s_phi[qq][lane], accI);
         __syncthreads();
     }
     if (lane < ND) a.I[e * ND + lane] = accI;
