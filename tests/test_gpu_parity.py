@@ -428,3 +428,23 @@ def test_nonpositive_concentration_gives_nonfinite(call):
     U, Up, Y = md.initial_state()
     info = ctx.step(T(U), T(Up), T(Y.ravel()), None, pr.tol, pr.maxit)
     assert info["relres"] <= pr.tol
+
+
+def test_large_item_size_is_cut_to_the_lds_limit():
+    """PDG_OPT_SCHWARZ_ITEM_KB = 8192 asks for items of up to 256 FP64 tiles.
+    The plan cuts them to what one workgroup's LDS holds (here for the coarse
+    system of 3,840 dofs, 60 tile rows), and the solve agrees with the default
+    plan's."""
+    pr = problems.table1_problem(1024, 4, 2, n_steps=2)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(pr.n_dof)
+    res = {}
+    for kb in (128, 8192):
+        ctx = solver.from_problem(pr, device=DEV, options={_lib.PDG_OPT_SCHWARZ_ITEM_KB: kb})
+        x = T(np.zeros(pr.n_dof))
+        info = ctx.solve(T(b), x, 1e-10, 5000)
+        print(f"[item kb {kb}] iters {info['iters']} relres {info['relres']:.2e}", flush=True)
+        assert info["relres"] <= 1e-10
+        res[kb] = (info["iters"], N(x))
+    assert abs(res[128][0] - res[8192][0]) <= 1
+    assert rel_l2(res[8192][1], res[128][1]) < 1e-8
