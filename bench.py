@@ -35,9 +35,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "time per CN step & MDoF/s at relres 1e-10; PCG iters; % HBM roofline vs FP64"
 # Inside a timed region one Schwarz launch in TIMING_PERIOD carries dispatch
-# events: timing every launch adds about 6 us to each PCG iteration (5 % of a
-# step of the default workload).
-TIMING_PERIOD = 8
+# events.  Each timed launch adds about 6.5 us to its PCG iteration (timing
+# every launch would add 6 % to a step of the default workload); one in 32
+# adds about 0.2 %.
+TIMING_PERIOD = 32
 
 
 def log(*a):

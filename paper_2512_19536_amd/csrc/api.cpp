@@ -927,7 +927,15 @@ void pcg_begin(pdg_ctx *c, double *x, const double *b, bool step_mode, double *u
     R.active = true;
 }
 
-// Launches the next chunk of iterations and the copy of the device scalars.
+void launch_finish_of(pdg_ctx *c) {
+    HIPCHK(launch_finish(vec(c, c->w.x), c->run.x, wptr<int32_t>(c, c->w.elsys), c->mesh.nd, c->mesh.n_elem, c->sc,
+                         c->stream));
+}
+
+// Launches the next chunk of iterations, the copy of the iterate to the
+// caller's x and the copy of the device scalars.  The iterate is copied after
+// every chunk (a few microseconds), so when the poll finds every system
+// stopped the output is already complete: no further launch and wait.
 void pcg_launch(pdg_ctx *c) {
     PcgRun &R = c->run;
     const int count = std::min(R.next, R.maxit - R.j + 1);
@@ -943,6 +951,7 @@ void pcg_launch(pdg_ctx *c) {
         }
     }
     R.next = c->chunk;
+    launch_finish_of(c);
     HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, c->n_sys * sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
 }
 
@@ -968,9 +977,8 @@ pdg_status pcg_end(pdg_ctx *c, pdg_solve_info *info, int *bad_sys) {
     for (const DevScalars &h : c->last) max_it = std::max(max_it, h.iters);
     // Schwarz launches that did work: init + iterations 1..max iters
     harvest_timing(c, (size_t)max_it + 1);
-    HIPCHK(launch_finish(vec(c, c->w.x), R.x, wptr<int32_t>(c, c->w.elsys), c->mesh.nd, c->mesh.n_elem, c->sc, s));
+    // the caller's x was written after the last chunk, before the poll's wait
     c->last_true.assign(n_sys, -1.0);
-    if (!c->true_resid) HIPCHK(hipStreamSynchronize(s));  // outputs complete on return
     if (c->true_resid) {
         SpmvArgs t{};
         t.mode = SPMV_RESID;
