@@ -602,10 +602,9 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     for (int k = 0; k < RPT; ++k) accR[k] = 0;
     V bA[RPT], bB[RPT];
     const int npair = nj >> 1;
-    if (npair > 0) {
-        load(bA, j0);
-        load(bB, j0 + 1);
-    }
+    // the first one or two tiles are requested before x is gathered
+    load(bA, j0);
+    if (nj > 1) load(bB, j0 + 1);
     // BF16 tiles hold the scaled inverse C = D^{-1} K^{-1} D^{-1}: the products
     // run on D x and their results are scaled by D (rows past n have d = 0)
     constexpr bool kScaled = std::is_same<E, uint16_t>::value;
@@ -689,13 +688,21 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
             load(bB, J + 3);
             __builtin_amdgcn_sched_barrier(0);
         }
+        // last pair; with an odd count the last tile is requested as soon as
+        // buffer A is free, so its latency overlaps the pair's second tile
         tile_step(bA, jj);
+        __builtin_amdgcn_sched_barrier(0);
+        if (jj + 2 < nj) load(bA, j0 + jj + 2);
+        __builtin_amdgcn_sched_barrier(0);
         tile_step(bB, jj + 1);
         jj += 2;
-    }
-    if (jj < nj) {  // odd count: last tile on its own
-        load(bA, j0 + jj);
-        tile_step(bA, jj);
+        if (jj < nj) {
+            tile_step(bA, jj);
+            ++jj;
+        }
+    } else {  // a single tile
+        tile_step(bA, 0);
+        jj = 1;
     }
     // column partials of the item's tiles below the diagonal, in tile order;
     // the diagonal tile's belong to this item's own rows
