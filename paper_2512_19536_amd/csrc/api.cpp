@@ -751,9 +751,16 @@ UpdateArgs update_args(pdg_ctx *c, int init, double *x, double *r, DevScalars *s
     return u;
 }
 
+// The Schwarz kernel stores its partials in FP32 when both tile stores
+// accumulate in FP32 (the same rule as its template's partial type).
+bool f32_partials(const pdg_ctx *c) {
+    return store_kind(c->pc.local_prec) != STORE_F64 && store_kind(c->pc.coarse_prec) != STORE_F64;
+}
+
 // r: the residual the preconditioner acts on (read directly when B = I).
 PupdateArgs pupdate_args(pdg_ctx *c, int mode, double *out, const double *r, DevScalars *sc) {
     PupdateArgs p{};
+    p.f32part = f32_partials(c) ? 1 : 0;
     p.mode = mode;
     p.pre_rz = c->no_precond ? c->pre_rr : c->pre_rz;
     p.nd = c->mesh.nd;

@@ -145,6 +145,8 @@ struct alignas(64) ItemDesc {
 struct SchwarzArgs {
     int mode;               // 0 apply only, 1/2 inside PCG (also writes the (r, z) shares)
     int nd, n_sub, nq0;
+    // Row and column partials, stored in FP64, or in FP32 (the first half of
+    // each buffer) when both the local and the coarse store accumulate in FP32.
     double *part;                // [n_items][64] row partials
     double *colpart;             // [n_tiles_total][64] column partials (indexed by global tile index)
     double *itemdot;             // [n_items] shares of (r, z) + (r0, z0)
@@ -206,6 +208,7 @@ struct PupdateArgs {
                                  // row (base + j) % 64
     const double *part;          // Schwarz row partials
     const double *colpart;       // Schwarz column partials
+    int f32part;                 // 1: the Schwarz partials are stored in FP32
     const double *itemdot;
     const double *rrpart;        // update partials
     const double *bbpart;        // SpMV partials of the right-hand side (init only)

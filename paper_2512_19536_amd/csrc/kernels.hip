@@ -456,6 +456,13 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <typename E> struct AccT { using T = float; };
 template <> struct AccT<double> { using T = double; };
 
+// Storage type of the row and column partials: FP32 when every item of the
+// launch accumulates in FP32 (local and coarse store both below FP64), which
+// halves the bytes the apply writes; FP64 otherwise.
+template <typename EL, typename EC> struct PartT { using T = double; };
+template <> struct PartT<float, float> { using T = float; };
+template <> struct PartT<uint16_t, float> { using T = float; };
+
 // Load type per storage type; element c of a loaded vector as the
 // accumulation type.
 template <typename E> struct Ld;
@@ -556,7 +563,7 @@ __device__ inline double sys_input(const SchwarzArgs &a, int s, bool coarse, int
 // loads stay in flight across them.  Outputs: the item's row partial in yout,
 // the FP64 input entry of row I in *r_own (threads < 64), and in *dot_col the
 // thread's share of sum_J (x_J, column partial of J).
-template <typename E>
+template <typename E, typename P>
 __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ tiles, const ItemDesc &d,
                                     bool coarse, double *smem, int max_nj, double *yout, double *r_own,
                                     double *dot_col) {
@@ -715,8 +722,10 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
                        (double)cx[3 * TILE + tid];
             if (kScaled && j0 + jj2 < I) v *= (double)ds[(j0 + jj2) * TILE + tid];
             if (j0 + jj2 < I) {
-                a.colpart[(cbase + j0 + jj2) * TILE + tid] = v;
-                dcol = fma(x64[jj2 * TILE + tid], v, dcol);
+                // the share of (r, z) takes the partial as stored
+                const P vp = (P)v;
+                reinterpret_cast<P *>(a.colpart)[(cbase + j0 + jj2) * TILE + tid] = vp;
+                dcol = fma(x64[jj2 * TILE + tid], (double)vp, dcol);
             } else {
                 diag_add = v;
             }
@@ -766,6 +775,7 @@ void k_schwarz(SchwarzArgs a, int max_nj) {
     const int tid = threadIdx.x;
     const int s = d.s;
     const bool coarse = s >= a.n_sub;
+    using P = typename PartT<EL, EC>::T;
     double r_own = 0.0, dcol = 0.0;
     const EL *tl = reinterpret_cast<const EL *>(a.tiles_local);
     const EC *tc = reinterpret_cast<const EC *>(a.tiles_coarse);
@@ -773,21 +783,22 @@ void k_schwarz(SchwarzArgs a, int max_nj) {
         // BF16 local store: systems whose rounded inverse failed the
         // positive-definiteness check are stored in FP32
         if (!coarse && d.f32)
-            schwarz_item<float>(a, reinterpret_cast<const float *>(a.tiles_fallback), d, false, smem, max_nj,
-                                yout, &r_own, &dcol);
+            schwarz_item<float, P>(a, reinterpret_cast<const float *>(a.tiles_fallback), d, false, smem, max_nj,
+                                   yout, &r_own, &dcol);
         else if (!coarse)
-            schwarz_item<EL>(a, tl, d, false, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EL, P>(a, tl, d, false, smem, max_nj, yout, &r_own, &dcol);
         else
-            schwarz_item<EC>(a, tc, d, true, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EC, P>(a, tc, d, true, smem, max_nj, yout, &r_own, &dcol);
     } else {
         if (!coarse)
-            schwarz_item<EL>(a, tl, d, false, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EL, P>(a, tl, d, false, smem, max_nj, yout, &r_own, &dcol);
         else
-            schwarz_item<EC>(a, tc, d, true, smem, max_nj, yout, &r_own, &dcol);
+            schwarz_item<EC, P>(a, tc, d, true, smem, max_nj, yout, &r_own, &dcol);
     }
     if (tid < TILE) {
-        const double y = yout[tid];
-        a.part[(int64_t)item * TILE + tid] = y;
+        const P yp = (P)yout[tid];
+        const double y = (double)yp;
+        reinterpret_cast<P *>(a.part)[(int64_t)item * TILE + tid] = yp;
         if (a.mode != 0) {
             // this item's share of (r, z): row I times the row partial, plus the
             // column partials times their x_J
@@ -826,48 +837,60 @@ __device__ inline TileRow tile_row(const ZSrc &z) {
 // any further ones (16 per round) and adds all in a fixed order.
 constexpr int kTrFirst = 20;
 
-__device__ inline void tile_row_first(const PupdateArgs &a, const TileRow &t, int lane, double (&w)[kTrFirst]) {
+// The partials are loaded in their stored type P (FP32 or FP64) and widened
+// to FP64 only where they are added, so all of a round's loads are issued
+// before the first wait.
+template <typename P>
+__device__ inline void tile_row_first(const PupdateArgs &a, const TileRow &t, int lane, P (&w)[kTrFirst]) {
+    const P *pp = reinterpret_cast<const P *>(a.part);
+    const P *cp = reinterpret_cast<const P *>(a.colpart);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) w[u] = t.it0 + u < t.it1 ? a.part[(int64_t)(t.it0 + u) * TILE + lane] : 0.0;
+    for (int u = 0; u < 4; ++u) w[u] = t.it0 + u < t.it1 ? pp[(int64_t)(t.it0 + u) * TILE + lane] : P(0);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int I = t.K + 1 + u;
-        w[4 + u] = I < t.nt ? a.colpart[(t.cb + (int64_t)I * (I + 1) / 2 + t.K) * TILE + lane] : 0.0;
+        w[4 + u] = I < t.nt ? cp[(t.cb + (int64_t)I * (I + 1) / 2 + t.K) * TILE + lane] : P(0);
     }
 }
 
-__device__ inline double tile_row_rest(const PupdateArgs &a, const TileRow &t, int lane, const double (&w)[kTrFirst]) {
-    double v = (w[0] + w[1]) + (w[2] + w[3]);
-    for (int it = t.it0 + 4; it < t.it1; ++it) v += a.part[(int64_t)it * TILE + lane];
+template <typename P>
+__device__ inline double tile_row_rest(const PupdateArgs &a, const TileRow &t, int lane, const P (&w)[kTrFirst]) {
+    const P *pp = reinterpret_cast<const P *>(a.part);
+    const P *cp = reinterpret_cast<const P *>(a.colpart);
+    double v = ((double)w[0] + (double)w[1]) + ((double)w[2] + (double)w[3]);
+    for (int it = t.it0 + 4; it < t.it1; ++it) v += (double)pp[(int64_t)it * TILE + lane];
     const int K = t.K, nt = t.nt;
     const int64_t cb = t.cb;
     double c[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = w[4 + u] + w[12 + u];
+    for (int u = 0; u < 8; ++u) c[u] = (double)w[4 + u] + (double)w[12 + u];
     for (int I0 = K + 17; I0 < nt; I0 += 16) {
-        double x[16];
+        P x[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int I = I0 + u;
-            x[u] = I < nt ? a.colpart[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane] : 0.0;
+            x[u] = I < nt ? cp[(cb + (int64_t)I * (I + 1) / 2 + K) * TILE + lane] : P(0);
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) c[u & 7] += x[u];
+        for (int u = 0; u < 16; ++u) c[u & 7] += (double)x[u];
     }
     return v + (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
 }
 
+template <typename P>
 __device__ inline double tile_row_value(const PupdateArgs &a, const TileRow &t, int lane) {
-    double w[kTrFirst];
-    tile_row_first(a, t, lane, w);
-    return tile_row_rest(a, t, lane, w);
+    P w[kTrFirst];
+    tile_row_first<P>(a, t, lane, w);
+    return tile_row_rest<P>(a, t, lane, w);
 }
 
+template <typename P>
 __device__ inline double tile_row_value(const PupdateArgs &a, int rt, int lane) {
-    return tile_row_value(a, tile_row(a, rt), lane);
+    return tile_row_value<P>(a, tile_row(a, rt), lane);
 }
 
-template <int NQ>
+// P: the storage type of the Schwarz partials (PupdateArgs::f32part).
+template <int NQ, typename P>
 __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const int nd = a.nd;
     const int64_t n = a.n_elem * nd;
@@ -910,22 +933,22 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const TileRow c_tr = tile_row(zc);
     const int done_lo = (a.mode != 0 && threadIdx.x == 0) ? a.sc[bk.s_lo].done : 0;
     // the partials of the fine and the coarse value, requested together
-    double wf[kTrFirst], wc[kTrFirst];
-    if (fine) tile_row_first(a, f_tr, f_lane, wf);
-    if (c_val) tile_row_first(a, c_tr, c_lane, wc);
+    P wf[kTrFirst], wc[kTrFirst];
+    if (fine) tile_row_first<P>(a, f_tr, f_lane, wf);
+    if (c_val) tile_row_first<P>(a, c_tr, c_lane, wc);
     // this thread's share of the first system's (r, z) partials
     double rz_t = 0.0;
     if (a.mode != 0 && !a.pre_rz)
         rz_t = a.r_ident ? thread_sum_partials<256>(a.rrpart + bk.u0, bk.u1 - bk.u0, 1, 0)
                          : thread_sum_partials<256>(a.itemdot + bk.it0, bk.it1 - bk.it0, 1, 0);
     double zz = 0.0;
-    if (my >= 0) zz = a.r_ident ? a.r_ident[idx] : tile_row_rest(a, f_tr, f_lane, wf);
+    if (my >= 0) zz = a.r_ident ? a.r_ident[idx] : tile_row_rest<P>(a, f_tr, f_lane, wf);
     if (NQ > 0 && n_c <= KMAX) {
-        if (c_val) s_z0[threadIdx.x] = tile_row_rest(a, c_tr, c_lane, wc);
+        if (c_val) s_z0[threadIdx.x] = tile_row_rest<P>(a, c_tr, c_lane, wc);
         // more than 256 kept values (NQ = 35): the rest one by one
         for (int t = threadIdx.x + 256; t < n_c * NQ; t += 256) {
             const ZSrc zs = a.blk_csrc[(int64_t)blockIdx.x * (KMAX * NV) + t];
-            s_z0[t] = tile_row_value(a, tile_row(zs), zs.nl & 63);
+            s_z0[t] = tile_row_value<P>(a, tile_row(zs), zs.nl & 63);
         }
         __syncthreads();
     }
@@ -941,7 +964,7 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
 #pragma unroll
             for (int j = 0; j < NQ; ++j) {
                 const int gi = g0 + j;
-                zz = fma(Pr[j], tile_row_value(a, gi >> 6, gi & 63), zz);
+                zz = fma(Pr[j], tile_row_value<P>(a, gi >> 6, gi & 63), zz);
             }
         }
     }
@@ -1579,22 +1602,28 @@ hipError_t launch_schwarz(const SchwarzArgs &a, int grid, int local_store, int c
     return hipErrorInvalidValue;
 }
 
+template <typename P>
+static hipError_t pupdate_t(const PupdateArgs &a, dim3 g, dim3 b, hipStream_t s) {
+    switch (a.nq0) {
+    case 0: hipLaunchKernelGGL((k_pupdate<0, P>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pupdate<3, P>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pupdate<4, P>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_pupdate<6, P>), g, b, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_pupdate<10, P>), g, b, 0, s, a); break;
+    case 15: hipLaunchKernelGGL((k_pupdate<15, P>), g, b, 0, s, a); break;
+    case 20: hipLaunchKernelGGL((k_pupdate<20, P>), g, b, 0, s, a); break;
+    case 35: hipLaunchKernelGGL((k_pupdate<35, P>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_pupdate(const PupdateArgs &a, hipStream_t s) {
     const int64_t n = a.n_elem * a.nd;
     if (n <= 0) return hipSuccess;
     const dim3 g((unsigned)((n + 255) / 256)), b(256);
-    switch (a.nq0) {
-    case 0: hipLaunchKernelGGL((k_pupdate<0>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pupdate<3>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pupdate<4>), g, b, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_pupdate<6>), g, b, 0, s, a); break;
-    case 10: hipLaunchKernelGGL((k_pupdate<10>), g, b, 0, s, a); break;
-    case 15: hipLaunchKernelGGL((k_pupdate<15>), g, b, 0, s, a); break;
-    case 20: hipLaunchKernelGGL((k_pupdate<20>), g, b, 0, s, a); break;
-    case 35: hipLaunchKernelGGL((k_pupdate<35>), g, b, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (a.f32part) return pupdate_t<float>(a, g, b, s);
+    return pupdate_t<double>(a, g, b, s);
 }
 
 hipError_t launch_sum_partials(const double *part, const int32_t *ranges, int n_sys, int slot, DevScalars *sc,
