@@ -616,19 +616,35 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
     // run on D x and their results are scaled by D (rows past n have d = 0)
     constexpr bool kScaled = std::is_same<E, uint16_t>::value;
     const float *ds = kScaled ? a.dscale + d.rbase : nullptr;
+    // the scales of the item's columns and of row I, kept in LDS after the
+    // gather (the epilogue uses them again)
+    float *dsl = reinterpret_cast<float *>(colx + (size_t)max_nj * 4 * TILE);
+    float *dsI = dsl + (size_t)max_nj * TILE;
     // gather x over the item's tile columns and over tile row I
     const int base = j0 * TILE;
     for (int t = tid; t < nj * TILE; t += 256) {
         const int gi = base + t;
         const double v = gi < n ? sys_input(a, s, coarse, dof0, gi) : 0.0;
         x64[t] = v;
-        if (sizeof(A) != 8) xa[t] = (A)(kScaled ? v * (double)ds[gi] : v);
+        if constexpr (kScaled) {
+            const float dv = ds[gi];
+            dsl[t] = dv;
+            xa[t] = (A)(v * (double)dv);
+        } else if (sizeof(A) != 8) {
+            xa[t] = (A)v;
+        }
     }
     if (tid < TILE) {
         const int gi = I * TILE + tid;
         const double v = gi < n ? sys_input(a, s, coarse, dof0, gi) : 0.0;
         xI64[tid] = v;
-        if (sizeof(A) != 8) xIa[tid] = (A)(kScaled ? v * (double)ds[gi] : v);
+        if constexpr (kScaled) {
+            const float dv = ds[gi];
+            dsI[tid] = dv;
+            xIa[tid] = (A)(v * (double)dv);
+        } else if (sizeof(A) != 8) {
+            xIa[tid] = (A)v;
+        }
         *r_own = v;
     }
     __syncthreads();
@@ -720,7 +736,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
             const A *cx = colx + jj2 * 4 * TILE;
             double v = (double)cx[tid] + (double)cx[TILE + tid] + (double)cx[2 * TILE + tid] +
                        (double)cx[3 * TILE + tid];
-            if (kScaled && j0 + jj2 < I) v *= (double)ds[(j0 + jj2) * TILE + tid];
+            if (kScaled && j0 + jj2 < I) v *= (double)dsl[jj2 * TILE + tid];
             if (j0 + jj2 < I) {
                 // the share of (r, z) takes the partial as stored
                 const P vp = (P)v;
@@ -741,7 +757,7 @@ __device__ inline void schwarz_item(const SchwarzArgs &a, const E *__restrict__ 
         A y = 0;
         const int arg = ar / RPT, ak = ar % RPT;
         for (int c = 0; c < NC; ++c) y += sR[(arg * NC + c) * RPT + ak];
-        yout[ar] = kScaled ? ((double)y + diag_add) * (double)ds[I * TILE + ar] : (double)y + diag_add;
+        yout[ar] = kScaled ? ((double)y + diag_add) * (double)dsI[ar] : (double)y + diag_add;
     }
     __syncthreads();
 }
@@ -1543,21 +1559,22 @@ template <typename E> static constexpr size_t scratch_bytes() {
 
 // x (FP64, columns + row I), x in the accumulation type, column exchange
 // [2][4][64]; the final row reduction (256 * RPT values) reuses the same space
-static size_t lds_need(size_t acc, size_t scratch, int max_nj) {
+static size_t lds_need(size_t acc, size_t scratch, int max_nj, bool scaled) {
     size_t b = (size_t)(max_nj + 1) * TILE * 8 + (acc == 8 ? 0 : (size_t)(max_nj + 1) * TILE * acc);
     b = (b + 15) & ~(size_t)15;
     const size_t x_end = (acc == 8 ? 1 : 3) * (size_t)(max_nj + 1) * TILE * acc;  // offset of the exchange area
     if (x_end > b) b = x_end;
     b += (size_t)max_nj * 4 * TILE * acc;  // per-tile column sums of the four wavefronts
+    if (scaled) b += (size_t)(max_nj + 1) * TILE * 4;  // BF16 store: column and row scales
     return b > scratch ? b : scratch;
 }
 
 template <typename EL, typename EC>
 static size_t schwarz_bytes_t(int max_nj) {
-    size_t bl = lds_need(acc_size<EL>(), scratch_bytes<EL>(), max_nj);
-    const size_t bc = lds_need(acc_size<EC>(), scratch_bytes<EC>(), max_nj);
+    size_t bl = lds_need(acc_size<EL>(), scratch_bytes<EL>(), max_nj, std::is_same<EL, uint16_t>::value);
+    const size_t bc = lds_need(acc_size<EC>(), scratch_bytes<EC>(), max_nj, false);
     if (std::is_same<EL, uint16_t>::value) {  // FP32-stored fallback systems
-        const size_t bf = lds_need(acc_size<float>(), scratch_bytes<float>(), max_nj);
+        const size_t bf = lds_need(acc_size<float>(), scratch_bytes<float>(), max_nj, false);
         bl = bl > bf ? bl : bf;
     }
     return bl > bc ? bl : bc;
