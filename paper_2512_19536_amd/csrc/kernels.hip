@@ -429,16 +429,33 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
             }
         }
         if (NQ > 0) {
-            double tot[NV];
-            block_sum<NV, 128>(v, tot);
-            if (threadIdx.x == 0)
+            if (c + 1 == c_end) {
+                // the last chunk's shares and the workgroup's ||r||^2 in one
+                // reduction (each component is summed as it would be alone)
+                double vv[NV + 1], tot[NV + 1];
 #pragma unroll
-                for (int j = 0; j < NQ; ++j) a.r0part[c * NQ + j] = tot[j];
+                for (int j = 0; j < NV; ++j) vv[j] = v[j];
+                vv[NV] = rr;
+                block_sum<NV + 1, 128>(vv, tot);
+                if (threadIdx.x == 0) {
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) a.r0part[c * NQ + j] = tot[j];
+                    a.rrpart[wg] = tot[NV];
+                }
+            } else {
+                double tot[NV];
+                block_sum<NV, 128>(v, tot);
+                if (threadIdx.x == 0)
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) a.r0part[c * NQ + j] = tot[j];
+            }
         }
     }
-    double v1[1] = {rr}, t1[1];
-    block_sum<1, 128>(v1, t1);
-    if (threadIdx.x == 0) a.rrpart[wg] = t1[0];
+    if (NQ == 0 || c_begin == c_end) {
+        double v1[1] = {rr}, t1[1];
+        block_sum<1, 128>(v1, t1);
+        if (threadIdx.x == 0) a.rrpart[wg] = t1[0];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -948,6 +965,25 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     const int c_lane = zc.nl & 63;
     const TileRow c_tr = tile_row(zc);
     const int done_lo = (a.mode != 0 && threadIdx.x == 0) ? a.sc[bk.s_lo].done : 0;
+    // The first system's iteration index and (r, z) of both parities (the owner
+    // block writes only the parity of this iteration, which is not used here),
+    // and, for small NQ, this dof's row of P and its coarse element: none
+    // depends on this launch's sums, so they are requested before its barriers.
+    int j_lo = 0;
+    double rz_lo_even = 0.0, rz_lo_odd = 0.0;
+    if (a.mode == 2) {
+        j_lo = a.sc[bk.s_lo].jcur;
+        rz_lo_even = a.sc[bk.s_lo].rz[0];
+        rz_lo_odd = a.sc[bk.s_lo].rz[1];
+    }
+    constexpr bool kEarlyP = NQ > 0 && NQ <= 4;
+    double Pe[kEarlyP ? NQ : 1];
+    int ce_e = 0;
+    if (kEarlyP && in) {
+        ce_e = a.elem_coarse[idx / nd];
+#pragma unroll
+        for (int j = 0; j < (kEarlyP ? NQ : 1); ++j) Pe[j] = a.P[idx * NQ + j];
+    }
     // the partials of the fine and the coarse value, requested together
     P wf[kTrFirst], wc[kTrFirst];
     if (fine) tile_row_first<P>(a, f_tr, f_lane, wf);
@@ -970,17 +1006,18 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
     }
     if (NQ > 0 && my >= 0) {
         const int64_t e = idx / nd;
-        const int ce = a.elem_coarse[e];
+        const int ce = kEarlyP ? ce_e : a.elem_coarse[e];
         const double *Pr = a.P + idx * NQ;
         if (n_c <= KMAX) {
 #pragma unroll
-            for (int j = 0; j < NQ; ++j) zz = fma(Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
+            for (int j = 0; j < NQ; ++j)
+                zz = fma(kEarlyP ? Pe[j % (kEarlyP ? NQ : 1)] : Pr[j], s_z0[(ce - c_lo) * NQ + j], zz);
         } else {
             const int g0 = a.coarse_base[ce];
 #pragma unroll
             for (int j = 0; j < NQ; ++j) {
                 const int gi = g0 + j;
-                zz = fma(Pr[j], tile_row_value<P>(a, gi >> 6, gi & 63), zz);
+                zz = fma(kEarlyP ? Pe[j % (kEarlyP ? NQ : 1)] : Pr[j], tile_row_value<P>(a, gi >> 6, gi & 63), zz);
             }
         }
     }
@@ -1001,8 +1038,9 @@ __global__ __launch_bounds__(256) void k_pupdate(PupdateArgs a) {
                          : block_total<256>(first ? rz_t
                                                   : thread_sum_partials<256>(a.r_ident ? a.rrpart + it0 : a.itemdot + it0,
                                                                              it1 - it0, 1, 0));
-            const int j = a.mode == 2 ? sc->jcur : 0;
-            const double bt = a.mode == 2 ? rz / sc->rz[(j - 1) & 1] : 0.0;
+            const int j = a.mode == 2 ? (first ? j_lo : sc->jcur) : 0;
+            const double bt =
+                a.mode == 2 ? rz / (first ? ((j - 1) & 1 ? rz_lo_odd : rz_lo_even) : sc->rz[(j - 1) & 1]) : 0.0;
             if (my == b) {
                 beta = bt;
                 active = true;
